@@ -1,0 +1,128 @@
+"""Seeded synthetic inputs: initial velocity fields for periodic boxes.
+
+This module holds no arithmetic of the lattice Boltzmann method itself; it
+only builds velocity fields u[3][nz][ny][nx] (float64, x fastest) that both
+the GPU path and its CPU checker start from.
+
+* ``taylor_green``: u = (U sin x cos y cos z, -U cos x sin y cos z, 0) with
+  node coordinates x_j = 2 pi j / N (no half-cell offset).
+* ``hit``: decaying homogeneous isotropic turbulence, a random solenoidal
+  field whose shell spectrum follows E(k) ~ k^4 exp(-2 (k/k0)^2), the shape
+  of the paper's narrow-band initial spectrum (section V.D), scaled to a
+  given r.m.s. velocity u' = sqrt(<|u|^2>/3).
+* ``kida``: the Kida vortex of section V.
+* ``shear_wave``: u_x = U sin(2 pi y / N_y), the viscosity probe.
+* ``smooth_random``: a few random Fourier modes on any (ragged) box.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _coords(n: int) -> np.ndarray:
+    return 2.0 * np.pi * np.arange(n) / n
+
+
+def _shape3(shape):
+    if np.isscalar(shape):
+        return int(shape), int(shape), int(shape)
+    nx, ny, nz = (int(s) for s in shape)
+    return nx, ny, nz
+
+
+def taylor_green(shape, U: float = 0.05) -> np.ndarray:
+    nx, ny, nz = _shape3(shape)
+    x = _coords(nx)[None, None, :]
+    y = _coords(ny)[None, :, None]
+    z = _coords(nz)[:, None, None]
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = U * np.sin(x) * np.cos(y) * np.cos(z)
+    u[1] = -U * np.cos(x) * np.sin(y) * np.cos(z)
+    return u
+
+
+def kida(shape, U0: float = 0.05) -> np.ndarray:
+    nx, ny, nz = _shape3(shape)
+    x = _coords(nx)[None, None, :]
+    y = _coords(ny)[None, :, None]
+    z = _coords(nz)[:, None, None]
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = U0 * np.sin(x) * (np.cos(3 * y) * np.cos(z) - np.cos(y) * np.cos(3 * z))
+    u[1] = U0 * np.sin(y) * (np.cos(3 * z) * np.cos(x) - np.cos(z) * np.cos(3 * x))
+    u[2] = U0 * np.sin(z) * (np.cos(3 * x) * np.cos(y) - np.cos(x) * np.cos(3 * y))
+    return u
+
+
+def shear_wave(shape, U: float = 1e-3) -> np.ndarray:
+    nx, ny, nz = _shape3(shape)
+    y = _coords(ny)[None, :, None]
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = U * np.sin(y) * np.ones((nz, 1, nx))
+    return u
+
+
+def hit(n, k0: float = 4.0, u_rms: float = 0.04, seed: int = 0) -> np.ndarray:
+    """Random solenoidal field with shell spectrum ~ k^4 exp(-2 (k/k0)^2).
+
+    White Gaussian noise is transformed, projected onto the plane normal to
+    each wave vector, and every integer shell round(|k|) is rescaled so its
+    energy follows the target spectrum; the inverse transform is real because
+    all operations respect Hermitian symmetry.  The mean is removed and the
+    field is scaled to the requested per-component r.m.s. value.
+    """
+    nx, ny, nz = _shape3(n)
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((3, nz, ny, nx))
+    wh = np.fft.fftn(w, axes=(1, 2, 3))
+    kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
+    ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
+    kx = np.fft.fftfreq(nx, 1.0 / nx)[None, None, :]
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    kvec = np.stack(np.broadcast_arrays(kx, ky, kz)).astype(np.float64)
+    k2s = np.where(k2 == 0, 1.0, k2)
+    kdotw = (kvec * wh).sum(axis=0)
+    wh = wh - kvec * kdotw / k2s
+    wh[:, k2 == 0] = 0.0
+    # the Nyquist planes of an even-sized grid are their own conjugate
+    # partners, where the projection cannot stay Hermitian: drop them
+    nyq = np.zeros(k2.shape, dtype=bool)
+    for kv, n_ in ((kx, nx), (ky, ny), (kz, nz)):
+        if n_ % 2 == 0:
+            nyq |= np.broadcast_to(np.abs(kv) == n_ // 2, k2.shape)
+    wh[:, nyq] = 0.0
+    kmag = np.sqrt(k2)
+    shell = np.rint(kmag).astype(np.int64)
+    e_now = np.bincount(shell.ravel(), weights=(np.abs(wh) ** 2).sum(axis=0).ravel())
+    kk = np.arange(e_now.size, dtype=np.float64)
+    e_target = kk ** 4 * np.exp(-2.0 * (kk / k0) ** 2)
+    scale = np.zeros_like(e_now)
+    ok = e_now > 0
+    scale[ok] = np.sqrt(e_target[ok] / e_now[ok])
+    wh = wh * scale[shell][None]
+    u = np.real(np.fft.ifftn(wh, axes=(1, 2, 3)))
+    u -= u.mean(axis=(1, 2, 3), keepdims=True)
+    rms = np.sqrt((u ** 2).sum(axis=0).mean() / 3.0)
+    return np.ascontiguousarray(u * (u_rms / rms))
+
+
+def smooth_random(shape, amplitude: float = 0.03, modes: int = 4, seed: int = 0) -> np.ndarray:
+    """Sum of a few random low-wavenumber sinusoids per component."""
+    nx, ny, nz = _shape3(shape)
+    rng = np.random.default_rng(seed)
+    x = _coords(nx)[None, None, :]
+    y = _coords(ny)[None, :, None]
+    z = _coords(nz)[:, None, None]
+    u = np.zeros((3, nz, ny, nx))
+    for a in range(3):
+        for _ in range(modes):
+            kx, ky, kz = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            amp = rng.uniform(-1, 1) * amplitude / modes
+            u[a] += amp * np.sin(kx * x + ky * y + kz * z + ph)
+    return u
+
+
+def random_density(shape, amplitude: float = 0.01, seed: int = 0) -> np.ndarray:
+    nx, ny, nz = _shape3(shape)
+    rng = np.random.default_rng(seed + 7919)
+    return 1.0 + amplitude * rng.uniform(-1, 1, size=(nz, ny, nx))

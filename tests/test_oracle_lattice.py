@@ -1,0 +1,185 @@
+"""Pins of the oracle's lattice-level behaviour: closed forms, invariants,
+hydrodynamic limits and the stability contrast the paper reports."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1507_02518_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_taylor_green_initial_energy_and_enstrophy(orc):
+    """k(0) = U^2/8; with second-order central differences the curl of the
+    Taylor-Green field carries sin(2 pi/N) in place of 2 pi/N, giving
+    Omega(0) = (3/8) U^2 sin^2(2 pi/N)."""
+    for n in [8, 16, 32]:
+        U = 0.05
+        u = inputs.taylor_green(n, U)
+        F = orc.init_feq(u)
+        _, u0 = orc.macros(F)
+        assert orc.energy(u0) == pytest.approx(U * U / 8, rel=1e-13)
+        assert orc.enstrophy(u0) == pytest.approx(0.375 * U * U * np.sin(2 * np.pi / n) ** 2,
+                                                  rel=1e-12)
+
+
+def test_mass_and_momentum_conserved_on_lattice(orc):
+    u = inputs.hit(12, 3.0, 0.05, seed=3)
+    rho = inputs.random_density(12, 0.02, seed=3)
+    F = orc.init_feq(u, rho)
+    v = orc.velocities().astype(np.float64)
+    m0 = F.sum()
+    j0 = np.einsum("ia,izyx->a", v, F)
+    F = orc.run(F, orc.beta_from_nu(1e-4), 40)
+    assert abs(F.sum() - m0) < 1e-13 * m0
+    assert np.abs(np.einsum("ia,izyx->a", v, F) - j0).max() < 1e-13 * m0
+
+
+@pytest.mark.parametrize("variant,gamma", [(3, None), (0, None), (3, 2.0)])
+def test_shear_wave_decays_at_the_lattice_viscosity(orc, variant, gamma):
+    """u_x = U sin(2 pi y/N) decays as exp(-nu k^2 t) with
+    nu = c_s^2 (1/(2 beta) - 1/2), for any stabilizer gamma."""
+    N, U = 64, 1e-3
+    y = np.arange(N)
+    s = np.sin(2 * np.pi * y / N)
+    for nu in [0.01, 0.1]:
+        F = orc.init_feq(inputs.shear_wave((1, N, 1), U))
+        amps = []
+
+        def cb(t, F):
+            if t % 10 == 0 and t >= 50:
+                _, uu = orc.macros(F)
+                amps.append((t, 2.0 / N * (uu[0, 0, :, 0] * s).sum()))
+
+        orc.run(F, orc.beta_from_nu(nu), 400, variant=variant, gamma=gamma, callback=cb)
+        a = np.array(amps)
+        rate = -np.polyfit(a[:, 0], np.log(a[:, 1]), 1)[0]
+        assert rate / (2 * np.pi / N) ** 2 == pytest.approx(nu, rel=5e-3)
+
+
+def test_taylor_green_decay_rate_converges_at_second_order(orc):
+    """Low-Re Taylor-Green: k(t) ~ exp(-2 nu |k|^2 t), |k|^2 = 3 (2 pi/N)^2.
+    The fitted rate approaches it with an error falling as N^-2."""
+    errs = []
+    nu = 0.02
+    for n in [12, 24]:
+        steps = int(round(100 * (n / 16) ** 2))
+        F = orc.init_feq(inputs.taylor_green(n, 1e-3))
+        es = []
+
+        def cb(t, F):
+            _, uu = orc.macros(F)
+            es.append(orc.energy(uu))
+
+        orc.run(F, orc.beta_from_nu(nu), steps, callback=cb)
+        t = np.arange(len(es))
+        sel = t >= steps // 4
+        rate = -np.polyfit(t[sel], np.log(np.array(es)[sel]), 1)[0]
+        errs.append(abs(rate / (6 * nu * (2 * np.pi / n) ** 2) - 1.0))
+    assert errs[1] < 0.02
+    assert 3.0 < errs[0] / errs[1] < 5.5
+
+
+def _swap_xy_u(u):
+    out = np.empty_like(u)
+    out[0] = np.swapaxes(u[1], 1, 2)
+    out[1] = np.swapaxes(u[0], 1, 2)
+    out[2] = np.swapaxes(u[2], 1, 2)
+    return out
+
+
+def _reflect_x_u(u):
+    idx = (-np.arange(u.shape[3])) % u.shape[3]
+    out = u[:, :, :, idx].copy()
+    out[0] *= -1
+    return out
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_lattice_symmetry_equivariance(orc, variant):
+    """Swapping x<->y, or reflecting x -> -x, commutes with the dynamics."""
+    n = 10
+    u = inputs.smooth_random(n, 0.05, seed=11)
+    beta = orc.beta_from_nu(5e-4)
+    _, ua = orc.macros(orc.run(orc.init_feq(u), beta, 12, variant=variant))
+    for op in (_swap_xy_u, _reflect_x_u):
+        _, ub = orc.macros(orc.run(orc.init_feq(op(u)), beta, 12, variant=variant))
+        assert np.abs(ub - op(ua)).max() < 1e-13
+
+
+def test_kbc_stays_stable_where_lbgk_fails(orc):
+    """Under-resolved decaying turbulence at very low viscosity: the entropic
+    stabilizer keeps the run finite and dissipative while LBGK (gamma = 2)
+    diverges, the contrast of section V."""
+    u = inputs.hit(16, 2.0, 0.05, seed=0)
+    F0 = orc.init_feq(u)
+    beta = orc.beta_from_nu(1e-5)
+    _, u0 = orc.macros(F0)
+    k0 = orc.energy(u0)
+    with np.errstate(all="ignore"):
+        Fk = orc.run(F0, beta, 250)
+        Fl = orc.run(F0, beta, 250, gamma=2.0)
+        _, uk = orc.macros(Fk)
+        _, ul = orc.macros(Fl)
+        kk, kl = orc.energy(uk), orc.energy(ul)
+    assert np.isfinite(Fk).all() and 0.0 < kk < k0
+    assert not (np.isfinite(kl) and kl < k0)
+
+
+def test_spectrum_parseval_and_single_mode(orc):
+    u = inputs.hit(16, 3.0, 0.04, seed=5)
+    E = orc.spectrum(u)
+    assert E.sum() == pytest.approx(orc.energy(u), rel=1e-12)
+    # one Fourier mode of |k| = 3 puts all energy in shell 3
+    n = 16
+    x = 2 * np.pi * np.arange(n) / n
+    w = np.zeros((3, n, n, n))
+    w[1] = 0.01 * np.sin(3 * x)[None, None, :]
+    E = orc.spectrum(w)
+    assert E[3] == pytest.approx(orc.energy(w), rel=1e-12)
+    assert E.sum() - E[3] < 1e-20
+
+
+def test_hit_input_is_solenoidal_with_target_spectrum(orc):
+    n, k0 = 24, 4.0
+    u = inputs.hit(n, k0, 0.04, seed=1)
+    uh = np.fft.fftn(u, axes=(1, 2, 3))
+    k = np.fft.fftfreq(n, 1.0 / n)
+    div = (k[None, None, :] * uh[0] + k[None, :, None] * uh[1] + k[:, None, None] * uh[2])
+    assert np.abs(div).max() < 1e-10 * np.abs(uh).max()
+    assert np.sqrt((u ** 2).sum(0).mean() / 3) == pytest.approx(0.04, rel=1e-12)
+    E = orc.spectrum(u)
+    kk = np.arange(1, 10)
+    target = kk ** 4 * np.exp(-2 * (kk / k0) ** 2)
+    ratio = E[1:10] / target
+    assert np.allclose(ratio, ratio[0], rtol=1e-9)
+
+
+def test_oracle_reproduces_committed_taylor_green_series(orc):
+    """Regression anchor: k(t), t = 0..100, of the 32^3 Taylor-Green run
+    (U = 0.05, nu = 0.001), written by tests/golden/make_oracle_golden.py."""
+    ref = np.loadtxt(os.path.join(GOLDEN, "oracle_tg32_energy.txt"))
+    F = orc.init_feq(inputs.taylor_green(32, 0.05))
+    es = []
+
+    def cb(t, F):
+        _, uu = orc.macros(F)
+        es.append(orc.energy(uu))
+
+    orc.run(F, orc.beta_from_nu(0.001), 100, callback=cb)
+    assert np.allclose(np.array(es), ref[:, 1], rtol=1e-13, atol=0)
+
+
+def test_shear_wave_is_carried_by_a_uniform_flow(orc):
+    """Galilean check of the propagation direction: with a uniform velocity V
+    along y, the shear wave u_x = U sin(k y) moves to +y by V t."""
+    N, U, V, steps = 32, 1e-3, 0.05, 200
+    u = inputs.shear_wave((1, N, 1), U)
+    u[1] += V
+    F = orc.run(orc.init_feq(u), orc.beta_from_nu(0.01), steps)
+    _, ut = orc.macros(F)
+    c = np.fft.fft(ut[0, 0, :, 0])[1]
+    c0 = np.fft.fft(u[0, 0, :, 0])[1]
+    shift = -np.angle(c / c0) / (2 * np.pi / N)
+    assert shift == pytest.approx(V * steps, rel=2e-3)
