@@ -1,0 +1,219 @@
+"""Throughput of the fused D3Q27 KBC stream+collide step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload (synthetic, seeded): a 256^3 periodic box of decaying homogeneous
+isotropic turbulence, initial spectrum E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4,
+u_rms = 0.04, rho = 1, nu = 5e-4, populations at the product-form
+equilibrium; KBC model s = d+t+q with the entropic stabilizer.  One step is
+one launch of the fused kernel over all 16.8 M nodes.  The headline line is
+FP64 storage with pull streaming (the form matched element-wise to the CPU
+oracle); the other storage forms are measured on the same field and listed
+under "forms".
+
+Prints one JSON line with MLUPS, the roofline of the step kernel (HBM bound,
+algorithmic bytes 2 * 27 * bytes-per-population per node and step, timed with
+HIP events on the stream the kernel runs on), and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+N = 256
+NU = 5e-4
+K0 = 4.0
+URMS = 0.04
+SEED = 0
+METRIC = "MLUPS + HBM-roofline %, D3Q27 KBC 256^3; ensemble p50/p99 vs plain loop"
+COUNTERS = os.path.join(ROOT, "profiles", "step_f64_pull_256_counters.txt")
+CSRC = os.path.join(ROOT, "paper_1507_02518_amd", "csrc")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_counters():
+    """HBM bytes per step launch from the committed rocprofv3 --pmc summary,
+    or None if it is absent or was taken on different kernel sources."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup):
+    stream = torch.cuda.current_stream()
+    with kbc.Box(N, NU, dtype, streaming=streaming, stream=stream.cuda_stream) as box:
+        kbc.kbc_init_velocity_device(box.h, u_dev.data_ptr(), None)
+        box.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        box.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1) / steps
+        bpn = box.bytes_per_node_step()
+        k = box.energy()
+    mlups = N ** 3 / (ms * 1e-3) / 1e6
+    gbs = bpn * N ** 3 / (ms * 1e-3) / 1e9
+    return {"ms_per_step": ms, "mlups": mlups, "algorithmic_GBs": gbs,
+            "frac_hbm_peak": gbs / PEAK_HBM_GBS, "bytes_per_node_step": bpn,
+            "wall_s": wall, "energy_after": k}
+
+
+def copy_ceiling(kbc, torch):
+    """Achievable HBM bandwidth of a plain streaming copy (2 x 2 GiB)."""
+    nbytes = 2 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        kbc.kbc_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        kbc.kbc_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(u, steps):
+    import oracle
+
+    F = oracle.init_feq(u)
+    beta = oracle.beta_from_nu(NU)
+    t0 = time.perf_counter()
+    oracle.run(F, beta, steps)
+    dt = time.perf_counter() - t0
+    return {"value": N ** 3 * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} step(s) of the same 256^3 HIT box, FP64, s=d+t+q, "
+                      f"{dt:.1f} s of CPU time on {oracle.num_threads()} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the KBC box runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1507_02518_amd import inputs, kbc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    kbc.load()
+
+    log(f"[bench] building the 256^3 HIT field (seed {SEED})")
+    u = inputs.hit(N, K0, URMS, seed=SEED)
+    u_dev = torch.from_numpy(u).cuda()
+
+    log("[bench] FP64 pull (headline)")
+    head = time_form(kbc, torch, u_dev, kbc.F64, kbc.PULL, args.steps, args.warmup)
+    log(f"[bench]   {head['mlups']:.0f} MLUPS, {head['algorithmic_GBs']:.0f} GB/s")
+
+    forms = {}
+    if not args.no_forms:
+        for name, dt, st in [("f64_aa", kbc.F64, kbc.AA), ("f32dev_pull", kbc.F32_DEV, kbc.PULL),
+                             ("f32dev_aa", kbc.F32_DEV, kbc.AA), ("f16dev_aa", kbc.F16_DEV, kbc.AA)]:
+            log(f"[bench] {name}")
+            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup)
+            forms[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+            log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
+    log("[bench] copy ceiling")
+    copy_gbs = copy_ceiling(kbc, torch)
+    del u_dev
+    torch.cuda.empty_cache()
+
+    traffic_bytes = read_counters()
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(head["algorithmic_GBs"], 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(head["algorithmic_GBs"] / PEAK_HBM_GBS, 4),
+        "traffic": traffic_bytes,
+        "kernel": "k_step<F64, d+t+q, pull>",
+        "bytes_per_node_step": head["bytes_per_node_step"],
+        "nodes_per_launch": N ** 3,
+        "copy_ceiling_GBs": round(copy_gbs, 1),
+        "frac_of_copy_ceiling": round(head["algorithmic_GBs"] / copy_gbs, 4),
+    }
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle sample ({args.cpu_steps} step(s) at 256^3)")
+        cpu = cpu_baseline(u, args.cpu_steps)
+        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "D3Q27 KBC (s=d+t+q, entropic gamma) step, 256^3 periodic "
+                               "decaying HIT, k0=4, u_rms=0.04, nu=5e-4, seed 0, FP64 pull",
+                   "nodes": N ** 3, "streaming": "pull", "storage": "f64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

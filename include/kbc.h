@@ -1,0 +1,170 @@
+/*
+ * kbc.h -- C-ABI of the MI355X D3Q27 KBC lattice Boltzmann library
+ * (libkbc.so, built from paper_1507_02518_amd/csrc for gfx950).
+ *
+ * The library advances the populations of a periodic box with the entropic
+ * multi-relaxation (KBC) scheme of Boesch, Chikatamarla & Karlin,
+ * "Entropic multi-relaxation lattice Boltzmann scheme for turbulent flows"
+ * (arXiv:1507.02518):
+ *   - propagation f_i(x + v_i, t+1) = f'_i(x, t) on the periodic lattice
+ *     (section I, Eq. Egeneral), D3Q27 velocities and weights (section II);
+ *   - per node the collision of section IV: conserved moments, product-form
+ *     equilibrium (Eq. entropic_eq), shear part s from table s_parts,
+ *     ds = s - s^eq, dh = f - f^eq - ds, stabilizer
+ *     gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> with the entropic scalar
+ *     product <X|Y> = sum_i X_i Y_i / f_i^eq (Eq. result21), and the relaxation
+ *     f' = f - beta (2 ds + gamma dh);
+ *   - beta from the viscosity, nu = c_s^2 (1/(2 beta) - 1/2), c_s^2 = 1/3
+ *     (Eqs. viscosity and sound).
+ *
+ * Conventions shared by every entry point
+ *   - Box shape is {nx, ny, nz}, each >= 1, nx*ny*nz < 2^31.
+ *   - Host scalar fields are FP64 [nz][ny][nx] with x fastest; host vector
+ *     fields are [3][nz][ny][nx]; host population fields are
+ *     [27][nz][ny][nx].  Velocity index i = (vx+1) + 3(vy+1) + 9(vz+1)
+ *     (rest population i = 13, opposite direction 26 - i).
+ *   - The state at time t is the pre-collision field F(t); one step is the
+ *     collision followed by propagation, so F(t+1)_i(x) = F'(t)_i(x - v_i).
+ *   - Host pointers are owned by the caller and only read or written during
+ *     the call.  Every call that returns host data synchronises the box's
+ *     stream; kbc_step only enqueues work.
+ *   - Every function returns 0 on success or a negative KBC_E* code; the
+ *     message of the last failure on the calling thread is kbc_last_error().
+ *     No C++ exception crosses this interface.
+ *   - One handle must not be used by two host threads at once.
+ */
+#ifndef KBC_H
+#define KBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KBC_OK 0
+#define KBC_EINVAL (-1)     /* bad argument: shape, nu, dtype, variant, NULL */
+#define KBC_ENOMEM (-2)     /* device allocation failed */
+#define KBC_EDEVICE (-3)    /* HIP runtime error (message in kbc_last_error) */
+#define KBC_EUNSTABLE (-4)  /* |u_a| >= 1 or rho <= 0 at init; non-finite state */
+#define KBC_ECAPACITY (-5)  /* pool budget or slots exhausted */
+#define KBC_ESTATE (-6)     /* call not valid in the current state */
+
+/* Storage precision of the populations.  KBC_F64 stores f_i in FP64 and
+ * collides in FP64.  The two deviation forms store f_i - W_i (FP32, or FP16
+ * times a per-direction power-of-two scale fixed at initialisation) and
+ * collide in FP32. */
+typedef enum { KBC_F64 = 0, KBC_F32_DEV = 1, KBC_F16_DEV = 2 } kbc_dtype;
+
+/* Shear part s of the natural-moment KBC models (section IV):
+ * s = d, d+t, d+q or d+t+q.  The paper's simulations use d+t+q. */
+typedef enum { KBC_S_D = 0, KBC_S_DT = 1, KBC_S_DQ = 2, KBC_S_DTQ = 3 } kbc_variant;
+
+/* Streaming pattern: two lattices with pull (gather) propagation, or one
+ * lattice updated in place with the AA access pattern.  Results are the
+ * same; AA halves the memory footprint. */
+typedef enum { KBC_PULL = 0, KBC_AA = 1 } kbc_streaming;
+
+typedef struct kbc_options {
+    int32_t variant;        /* kbc_variant; default KBC_S_DTQ */
+    int32_t streaming;      /* kbc_streaming; default KBC_PULL */
+    int32_t gamma_fixed;    /* 0: entropic gamma; 1: gamma = gamma_value */
+    int32_t device;         /* HIP device ordinal; -1 = current device */
+    double gamma_value;     /* used when gamma_fixed = 1 (2 = LBGK, 1/beta = RLB) */
+    double gamma_eps;       /* gamma = 2 where <dh|dh> <= gamma_eps * rho;
+                               <= 0 selects the default (1e-28 for FP64,
+                               1e-16 for the FP32 collision) */
+    void* stream;           /* hipStream_t to enqueue on (borrowed, must outlive
+                               the handle); NULL = the library creates one */
+} kbc_options;
+
+typedef struct kbc_box* kbc_handle;
+
+/* Fill *opt with the defaults listed above. */
+void kbc_options_default(kbc_options* opt);
+
+/* Create a box of shape {nx, ny, nz} with kinematic viscosity nu > 0
+ * (beta = 1/(6 nu + 1) in (0, 1)) and the given storage dtype.  opt may be
+ * NULL.  Allocates the device population buffers (two lattices for
+ * KBC_PULL, one for KBC_AA); the populations are undefined until
+ * kbc_init_velocity or kbc_set_populations.  On success *out owns the box. */
+int kbc_create(const int64_t shape[3], double nu, int32_t dtype,
+               const kbc_options* opt, kbc_handle* out);
+
+/* Release every device resource of the box.  NULL is accepted. */
+int kbc_destroy(kbc_handle h);
+
+/* F(0) = f^eq(rho, u) at every node (product-form equilibrium, section II),
+ * t = 0.  u: host [3][nz][ny][nx] FP64; rho: host [nz][ny][nx] FP64 or NULL
+ * for rho = 1.  Returns KBC_EUNSTABLE (state unchanged) if some |u_a| >= 1
+ * or rho <= 0, where the equilibrium is not positive. */
+int kbc_init_velocity(kbc_handle h, const double* u, const double* rho);
+
+/* Same, with u and rho already in device memory (same layouts). */
+int kbc_init_velocity_device(kbc_handle h, const double* u_dev, const double* rho_dev);
+
+/* Enqueue n >= 0 steps (one kernel launch per step) on the box's stream and
+ * return; t advances by n. */
+int kbc_step(kbc_handle h, int64_t n);
+
+/* Density and velocity of F(t) (section I: rho = sum_i f_i, rho u =
+ * sum_i v_i f_i) copied to host arrays rho [nz][ny][nx] and u [3][nz][ny][nx];
+ * either may be NULL.  Synchronises.  KBC_EUNSTABLE if any value is not
+ * finite (the arrays are still written). */
+int kbc_moments(kbc_handle h, double* rho, double* u);
+
+/* Kinetic energy k = (1/2) < |u - <u>|^2 > of F(t) (section V), <.> the mean
+ * over nodes, reduced in FP64 on the device in a fixed order (bitwise
+ * reproducible).  Synchronises.  KBC_EUNSTABLE if the state is not finite. */
+int kbc_energy(kbc_handle h, double* k);
+
+/* Enstrophy Omega = (1/2) < |curl u'|^2 >, u' = u - <u>, derivatives by
+ * second-order central differences on the periodic grid (section V.A).
+ * FP64, fixed reduction order.  Synchronises. */
+int kbc_enstrophy(kbc_handle h, double* omega);
+
+/* Copy F(t) to host f [27][nz][ny][nx] FP64 (deviation storage is decoded
+ * to full populations).  Synchronises. */
+int kbc_get_populations(kbc_handle h, double* f);
+
+/* Copy F(t) at `count` selected nodes to host f [count][27] FP64.  nodes
+ * holds linear node indices (x + nx*(y + ny*z)), each in [0, nx*ny*nz);
+ * returns KBC_EINVAL (nothing copied) if one is out of range.  Synchronises.
+ * Lets a caller check a large box at a few nodes without copying it whole. */
+int kbc_sample_populations(kbc_handle h, const int64_t* nodes, int64_t count, double* f);
+
+/* Replace the state by host f [27][nz][ny][nx] FP64 taken as F(t), and set
+ * the step counter to t >= 0.  Deviation storage rounds f_i - W_i to the
+ * storage precision (FP16 keeps the scales chosen at initialisation, or
+ * picks them from f when the box was never initialised). */
+int kbc_set_populations(kbc_handle h, const double* f, int64_t t);
+
+/* Current step counter. */
+int kbc_time(kbc_handle h, int64_t* t);
+
+/* Wait for every step enqueued on the box's stream. */
+int kbc_sync(kbc_handle h);
+
+/* HBM bytes one step moves per lattice node if each population is read and
+ * written exactly once (2 * 27 * bytes per stored population). */
+int kbc_bytes_per_node_step(kbc_handle h, double* bytes);
+
+/* The stream the box enqueues on (a hipStream_t). */
+int kbc_stream(kbc_handle h, void** stream);
+
+/* Measurement utility (not part of the method): copy `bytes` (a multiple of
+ * 16) from device src to device dst with a plain streaming kernel on the
+ * given hipStream_t (NULL = default stream), without synchronising.  Its
+ * duration and HBM counters give the achievable copy bandwidth and the
+ * scale of the rocprof FETCH_SIZE / WRITE_SIZE counters against known bytes. */
+int kbc_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next failing call on the same thread. */
+const char* kbc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KBC_H */

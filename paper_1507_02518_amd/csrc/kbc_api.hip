@@ -1,0 +1,508 @@
+// kbc_api.hip -- C-ABI of the D3Q27 KBC box (declared in include/kbc.h):
+// argument checking, device memory, the step counter and layout bookkeeping,
+// diagnostics read-back and error reporting.  Every computation on the
+// populations runs in the kernels of kbc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kbc.h"
+#include "kbc_internal.h"
+
+using namespace kbc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    if (e == hipErrorOutOfMemory) return fail(KBC_ENOMEM, std::string(where) + ": out of device memory");
+    return fail(KBC_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define KBC_HIP(call)                                         \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+    } while (0)
+
+size_t elem_bytes(int dtype)
+{
+    return dtype == KBC_F64 ? 8 : (dtype == KBC_F32_DEV ? 4 : 2);
+}
+
+}  // namespace
+
+struct kbc_box {
+    int64_t shape[3];
+    Geom g;
+    int dtype, variant, streaming;
+    Coll coll;
+    double nu;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    void* buf[2];       // pull: two lattices; AA: buf[0] only
+    int cur;            // pull: buffer holding P(t-1)
+    int64_t t;
+    float scale[27], inv_scale[27];
+    bool scales_set;
+    bool initialised;
+    // diagnostics scratch (allocated on first use)
+    double* d_u;
+    double* d_rho;
+    double* d_partial;
+    double* d_sum;      // [0..2] mean sums, [3..5] second reduction
+    int* d_flag;
+    unsigned* d_max;
+    double* d_pop;      // canonical staging [27][N]
+};
+
+namespace {
+
+int check_handle(kbc_handle h)
+{
+    if (!h) return fail(KBC_EINVAL, "null handle");
+    return KBC_OK;
+}
+
+int set_device(kbc_handle h)
+{
+    KBC_HIP(hipSetDevice(h->device));
+    return KBC_OK;
+}
+
+int layout_now(const kbc_box* h)
+{
+    if (h->streaming == KBC_PULL) return LY_PULL;
+    return (h->t % 2 == 0) ? LY_AA_EVEN : LY_AA_ODD;
+}
+
+void* state_buf(const kbc_box* h)
+{
+    return h->streaming == KBC_PULL ? h->buf[h->cur] : h->buf[0];
+}
+
+int ensure_diag(kbc_handle h, bool need_pop)
+{
+    const size_t N = h->g.nnodes;
+    if (!h->d_u) KBC_HIP(hipMalloc(&h->d_u, 3 * N * sizeof(double)));
+    if (!h->d_rho) KBC_HIP(hipMalloc(&h->d_rho, N * sizeof(double)));
+    if (!h->d_partial) KBC_HIP(hipMalloc(&h->d_partial, 3 * (size_t)reduce_partials() * sizeof(double)));
+    if (!h->d_sum) KBC_HIP(hipMalloc(&h->d_sum, 8 * sizeof(double)));
+    if (!h->d_flag) KBC_HIP(hipMalloc(&h->d_flag, sizeof(int)));
+    if (!h->d_max) KBC_HIP(hipMalloc(&h->d_max, 27 * sizeof(unsigned)));
+    if (need_pop && !h->d_pop) KBC_HIP(hipMalloc(&h->d_pop, 27 * N * sizeof(double)));
+    return KBC_OK;
+}
+
+// FP16 scales: a power of two per direction so that the largest deviation
+// maps to about 2^12, equal for opposite directions.
+void choose_scales(kbc_handle h, const unsigned* max_bits)
+{
+    for (int i = 0; i < 27; ++i) {
+        float m0, m1;
+        std::memcpy(&m0, &max_bits[i], sizeof(float));
+        std::memcpy(&m1, &max_bits[26 - i], sizeof(float));
+        double m = std::max<double>(m0, m1);
+        m = std::max(m, 1e-4 * weight(i));
+        const int e = (int)std::floor(std::log2(4096.0 / m));
+        h->scale[i] = std::ldexp(1.0f, e);
+        h->inv_scale[i] = std::ldexp(1.0f, -e);
+    }
+    h->scales_set = true;
+}
+
+// Moments of the current state into h->d_u / h->d_rho; returns KBC_EUNSTABLE
+// when a value is not finite.
+int compute_moments(kbc_handle h, bool want_rho)
+{
+    int r = ensure_diag(h, false);
+    if (r) return r;
+    KBC_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), h->stream));
+    KBC_HIP(launch_moments(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale,
+                           want_rho ? h->d_rho : nullptr, h->d_u, h->d_flag, h->stream));
+    int flag = 0;
+    KBC_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    if (flag) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
+    return KBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kbc_options_default(kbc_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->variant = KBC_S_DTQ;
+    opt->streaming = KBC_PULL;
+    opt->gamma_fixed = 0;
+    opt->device = -1;
+    opt->gamma_value = 2.0;
+    opt->gamma_eps = 0.0;
+    opt->stream = nullptr;
+}
+
+const char* kbc_last_error(void) { return g_last_error.c_str(); }
+
+int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_options* opt_in,
+               kbc_handle* out)
+{
+    if (!out) return fail(KBC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!shape) return fail(KBC_EINVAL, "shape is NULL");
+    kbc_options opt;
+    if (opt_in) opt = *opt_in;
+    else kbc_options_default(&opt);
+    for (int a = 0; a < 3; ++a)
+        if (shape[a] < 1) return fail(KBC_EINVAL, "shape entries must be >= 1");
+    const double nn = (double)shape[0] * (double)shape[1] * (double)shape[2];
+    if (nn >= 2147483648.0) return fail(KBC_EINVAL, "box has 2^31 nodes or more");
+    if (!(nu > 0.0) || !std::isfinite(nu)) return fail(KBC_EINVAL, "nu must be finite and > 0");
+    if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV)
+        return fail(KBC_EINVAL, "unknown dtype");
+    if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return fail(KBC_EINVAL, "unknown variant");
+    if (opt.streaming != KBC_PULL && opt.streaming != KBC_AA) return fail(KBC_EINVAL, "unknown streaming");
+    if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))
+        return fail(KBC_EINVAL, "gamma_value must be finite");
+
+    kbc_box* h = new (std::nothrow) kbc_box();
+    if (!h) return fail(KBC_ENOMEM, "host allocation failed");
+    std::memset(h, 0, sizeof(*h));
+    for (int a = 0; a < 3; ++a) h->shape[a] = shape[a];
+    h->g.nx = (uint32_t)shape[0];
+    h->g.ny = (uint32_t)shape[1];
+    h->g.nz = (uint32_t)shape[2];
+    h->g.nnodes = (uint32_t)(shape[0] * shape[1] * shape[2]);
+    h->g.dnx = make_fastdiv(h->g.nx);
+    h->g.dny = make_fastdiv(h->g.ny);
+    h->g.plane = h->g.nnodes;
+    h->dtype = dtype;
+    h->variant = opt.variant;
+    h->streaming = opt.streaming;
+    h->nu = nu;
+    // nu = c_s^2 (1/(2 beta) - 1/2), c_s^2 = 1/3
+    const double beta = 1.0 / (6.0 * nu + 1.0);
+    h->coll.beta = beta;
+    h->coll.inv_beta = 1.0 / beta;
+    h->coll.c2 = 2.0 - 1.0 / beta;
+    h->coll.gamma_eps = opt.gamma_eps > 0.0 ? opt.gamma_eps : (dtype == KBC_F64 ? 1e-28 : 1e-16);
+    h->coll.gamma_fixed = opt.gamma_fixed ? 1 : 0;
+    h->coll.gamma_value = opt.gamma_value;
+    for (int i = 0; i < 27; ++i) h->scale[i] = h->inv_scale[i] = 1.0f;
+
+    int dev = opt.device;
+    if (dev < 0) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "hipGetDevice");
+        }
+    }
+    h->device = dev;
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipSetDevice");
+    }
+    if (opt.stream) {
+        h->stream = (hipStream_t)opt.stream;
+        h->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        h->own_stream = true;
+    }
+    const size_t bytes = 27ull * h->g.nnodes * elem_bytes(dtype);
+    const int nbuf = h->streaming == KBC_PULL ? 2 : 1;
+    for (int b = 0; b < nbuf; ++b) {
+        e = hipMalloc(&h->buf[b], bytes);
+        if (e != hipSuccess) {
+            kbc_destroy(h);
+            return hip_fail(e, "hipMalloc(populations)");
+        }
+    }
+    *out = h;
+    return KBC_OK;
+}
+
+int kbc_destroy(kbc_handle h)
+{
+    if (!h) return KBC_OK;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : {h->buf[0], h->buf[1], (void*)h->d_u, (void*)h->d_rho, (void*)h->d_partial,
+                    (void*)h->d_sum, (void*)h->d_flag, (void*)h->d_max, (void*)h->d_pop})
+        if (p) (void)hipFree(p);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return KBC_OK;
+}
+
+static int init_from_device(kbc_handle h, const double* du, const double* drho)
+{
+    int r = ensure_diag(h, false);
+    if (r) return r;
+    KBC_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), h->stream));
+    KBC_HIP(launch_check_init(h->g, du, drho, h->d_flag, h->stream));
+    int flag = 0;
+    KBC_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    if (flag)
+        return fail(KBC_EUNSTABLE,
+                    "initial state has |u_a| >= 1 or rho <= 0 (equilibrium not positive)");
+    if (h->dtype == KBC_F16_DEV) {
+        KBC_HIP(launch_feq_dev_max(h->g, du, drho, h->d_max, h->stream));
+        unsigned mb[27];
+        KBC_HIP(hipMemcpyAsync(mb, h->d_max, sizeof(mb), hipMemcpyDeviceToHost, h->stream));
+        KBC_HIP(hipStreamSynchronize(h->stream));
+        choose_scales(h, mb);
+    }
+    h->t = 0;
+    h->cur = 0;
+    KBC_HIP(launch_init_feq(h->dtype, layout_now(h), state_buf(h), h->g, h->scale, du, drho,
+                            h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    h->initialised = true;
+    return KBC_OK;
+}
+
+int kbc_init_velocity(kbc_handle h, const double* u, const double* rho)
+{
+    if (int r = check_handle(h)) return r;
+    if (!u) return fail(KBC_EINVAL, "u is NULL");
+    if (int r = set_device(h)) return r;
+    int r = ensure_diag(h, false);
+    if (r) return r;
+    const size_t N = h->g.nnodes;
+    KBC_HIP(hipMemcpyAsync(h->d_u, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (rho) KBC_HIP(hipMemcpyAsync(h->d_rho, rho, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    return init_from_device(h, h->d_u, rho ? h->d_rho : nullptr);
+}
+
+int kbc_init_velocity_device(kbc_handle h, const double* u_dev, const double* rho_dev)
+{
+    if (int r = check_handle(h)) return r;
+    if (!u_dev) return fail(KBC_EINVAL, "u_dev is NULL");
+    if (int r = set_device(h)) return r;
+    return init_from_device(h, u_dev, rho_dev);
+}
+
+int kbc_step(kbc_handle h, int64_t n)
+{
+    if (int r = check_handle(h)) return r;
+    if (n < 0) return fail(KBC_EINVAL, "n must be >= 0");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state (call kbc_init_velocity)");
+    if (n == 0) return KBC_OK;
+    if (int r = set_device(h)) return r;
+    StepParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.g = h->g;
+    p.c = h->coll;
+    for (int i = 0; i < 27; ++i) {
+        p.scale[i] = h->scale[i];
+        p.inv_scale[i] = h->inv_scale[i];
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        int sweep;
+        if (h->streaming == KBC_PULL) {
+            sweep = SW_PULL;
+            p.src = h->buf[h->cur];
+            p.dst = h->buf[1 - h->cur];
+        } else {
+            sweep = (h->t % 2 == 0) ? SW_AA_EVEN : SW_AA_ODD;
+            p.src = h->buf[0];
+            p.dst = h->buf[0];
+        }
+        KBC_HIP(launch_step(h->dtype, h->variant, sweep, p, h->stream));
+        if (h->streaming == KBC_PULL) h->cur = 1 - h->cur;
+        h->t += 1;
+    }
+    return KBC_OK;
+}
+
+int kbc_moments(kbc_handle h, double* rho, double* u)
+{
+    if (int r = check_handle(h)) return r;
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    const int st = compute_moments(h, rho != nullptr);
+    if (st != KBC_OK && st != KBC_EUNSTABLE) return st;
+    const size_t N = h->g.nnodes;
+    if (rho) KBC_HIP(hipMemcpy(rho, h->d_rho, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (u) KBC_HIP(hipMemcpy(u, h->d_u, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+    if (st == KBC_EUNSTABLE) g_last_error = "state is not finite (the run has diverged)";
+    return st;
+}
+
+static int mean_sums(kbc_handle h)
+{
+    KBC_HIP(launch_reduce(0, h->g, h->d_u, nullptr, h->d_partial, h->d_sum, h->stream));
+    return KBC_OK;
+}
+
+int kbc_energy(kbc_handle h, double* k)
+{
+    if (int r = check_handle(h)) return r;
+    if (!k) return fail(KBC_EINVAL, "k is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    if (int r = compute_moments(h, false)) return r;
+    if (int r = mean_sums(h)) return r;
+    KBC_HIP(launch_reduce(1, h->g, h->d_u, h->d_sum, h->d_partial, h->d_sum + 3, h->stream));
+    double s = 0.0;
+    KBC_HIP(hipMemcpyAsync(&s, h->d_sum + 3, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    *k = 0.5 * s / (double)h->g.nnodes;
+    return KBC_OK;
+}
+
+int kbc_enstrophy(kbc_handle h, double* omega)
+{
+    if (int r = check_handle(h)) return r;
+    if (!omega) return fail(KBC_EINVAL, "omega is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    if (int r = compute_moments(h, false)) return r;
+    if (int r = mean_sums(h)) return r;
+    KBC_HIP(launch_reduce(2, h->g, h->d_u, h->d_sum, h->d_partial, h->d_sum + 3, h->stream));
+    double s = 0.0;
+    KBC_HIP(hipMemcpyAsync(&s, h->d_sum + 3, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    *omega = 0.5 * s / (double)h->g.nnodes;
+    return KBC_OK;
+}
+
+int kbc_get_populations(kbc_handle h, double* f)
+{
+    if (int r = check_handle(h)) return r;
+    if (!f) return fail(KBC_EINVAL, "f is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    if (int r = ensure_diag(h, true)) return r;
+    KBC_HIP(launch_gather_pop(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale, h->d_pop,
+                              h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    KBC_HIP(hipMemcpy(f, h->d_pop, 27ull * h->g.nnodes * sizeof(double), hipMemcpyDeviceToHost));
+    return KBC_OK;
+}
+
+int kbc_sample_populations(kbc_handle h, const int64_t* nodes, int64_t count, double* f)
+{
+    if (int r = check_handle(h)) return r;
+    if (count < 0 || count > (1 << 24)) return fail(KBC_EINVAL, "count must be in [0, 2^24]");
+    if (count == 0) return KBC_OK;
+    if (!nodes || !f) return fail(KBC_EINVAL, "nodes or f is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    std::vector<uint32_t> idx((size_t)count);
+    for (int64_t k = 0; k < count; ++k) {
+        if (nodes[k] < 0 || nodes[k] >= (int64_t)h->g.nnodes)
+            return fail(KBC_EINVAL, "node index out of range");
+        idx[(size_t)k] = (uint32_t)nodes[k];
+    }
+    if (int r = set_device(h)) return r;
+    uint32_t* d_idx = nullptr;
+    double* d_out = nullptr;
+    hipError_t e = hipMalloc(&d_idx, idx.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_out, idx.size() * 27 * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_idx, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess)
+        e = launch_sample_pop(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale, d_idx,
+                              (int)count, d_out, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f, d_out, idx.size() * 27 * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (d_idx) (void)hipFree(d_idx);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(e, "kbc_sample_populations");
+    return KBC_OK;
+}
+
+int kbc_set_populations(kbc_handle h, const double* f, int64_t t)
+{
+    if (int r = check_handle(h)) return r;
+    if (!f) return fail(KBC_EINVAL, "f is NULL");
+    if (t < 0) return fail(KBC_EINVAL, "t must be >= 0");
+    if (int r = set_device(h)) return r;
+    if (int r = ensure_diag(h, true)) return r;
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    KBC_HIP(hipMemcpy(h->d_pop, f, 27ull * h->g.nnodes * sizeof(double), hipMemcpyHostToDevice));
+    if (h->dtype == KBC_F16_DEV && !h->scales_set) {
+        KBC_HIP(launch_pop_dev_max(h->g, h->d_pop, h->d_max, h->stream));
+        unsigned mb[27];
+        KBC_HIP(hipMemcpyAsync(mb, h->d_max, sizeof(mb), hipMemcpyDeviceToHost, h->stream));
+        KBC_HIP(hipStreamSynchronize(h->stream));
+        choose_scales(h, mb);
+    }
+    h->t = t;
+    h->cur = 0;
+    KBC_HIP(launch_scatter_pop(h->dtype, layout_now(h), state_buf(h), h->g, h->scale, h->d_pop,
+                               h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    h->initialised = true;
+    return KBC_OK;
+}
+
+int kbc_time(kbc_handle h, int64_t* t)
+{
+    if (int r = check_handle(h)) return r;
+    if (!t) return fail(KBC_EINVAL, "t is NULL");
+    *t = h->t;
+    return KBC_OK;
+}
+
+int kbc_sync(kbc_handle h)
+{
+    if (int r = check_handle(h)) return r;
+    if (int r = set_device(h)) return r;
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    return KBC_OK;
+}
+
+int kbc_bytes_per_node_step(kbc_handle h, double* bytes)
+{
+    if (int r = check_handle(h)) return r;
+    if (!bytes) return fail(KBC_EINVAL, "bytes is NULL");
+    *bytes = 2.0 * 27.0 * (double)elem_bytes(h->dtype);
+    return KBC_OK;
+}
+
+int kbc_stream(kbc_handle h, void** stream)
+{
+    if (int r = check_handle(h)) return r;
+    if (!stream) return fail(KBC_EINVAL, "stream is NULL");
+    *stream = (void*)h->stream;
+    return KBC_OK;
+}
+
+int kbc_hbm_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (!dst || !src) return fail(KBC_EINVAL, "dst or src is NULL");
+    if (bytes % 16) return fail(KBC_EINVAL, "bytes must be a multiple of 16");
+    KBC_HIP(launch_copy16(dst, src, bytes / 16, (hipStream_t)stream));
+    return KBC_OK;
+}
+
+}  // extern "C"

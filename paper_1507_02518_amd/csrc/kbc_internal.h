@@ -1,0 +1,70 @@
+// kbc_internal.h -- host-side interface between the C-ABI layer and the
+// kernel launchers (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kbc_device.h"
+
+namespace kbc {
+
+// Population storage layout of one box (all modes are [27][nz][ny][nx]):
+//   pull:  buffer `cur` holds the post-collision P(t-1) so that
+//          F_i(x, t) = cur[i][x - v_i];
+//   AA:    even t: F_i(x, t) = buf[i][x]; odd t: F_i(x, t) = buf[26-i][x - v_i].
+enum Layout : int { LY_PULL = 0, LY_AA_EVEN = 1, LY_AA_ODD = 2 };
+
+// One time step of one box (src -> dst for pull; in place for AA).
+hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
+                       hipStream_t stream);
+
+// Write f^eq(rho, u) of device fields u [3][N], rho [N] (may be NULL) into the
+// storage buffer in the given layout.
+hipError_t launch_init_feq(int storage, int layout, void* buf, const Geom& g,
+                           const float* scale, const double* u, const double* rho,
+                           hipStream_t stream);
+
+// Validity of an initial state: sets *flag (device int, pre-zeroed) to 1 if
+// some |u_a| >= 1 or rho <= 0 or a value is not finite.
+hipError_t launch_check_init(const Geom& g, const double* u, const double* rho, int* flag,
+                             hipStream_t stream);
+
+// Per-direction max |f^eq_i - W_i| over the box (device float[27], zeroed
+// by the callee) for choosing FP16 scales.
+hipError_t launch_feq_dev_max(const Geom& g, const double* u, const double* rho,
+                              unsigned* max_bits, hipStream_t stream);
+
+// Per-direction max |f_i - W_i| of a canonical FP64 population field.
+hipError_t launch_pop_dev_max(const Geom& g, const double* f, unsigned* max_bits,
+                              hipStream_t stream);
+
+// Canonical F(t) [27][N] FP64 <-> storage in the given layout.
+hipError_t launch_gather_pop(int storage, int layout, const void* buf, const Geom& g,
+                             const float* inv_scale, double* f, hipStream_t stream);
+hipError_t launch_scatter_pop(int storage, int layout, void* buf, const Geom& g,
+                              const float* scale, const double* f, hipStream_t stream);
+
+// F(t) at selected nodes: out [count][27] FP64, nodes [count] (in range).
+hipError_t launch_sample_pop(int storage, int layout, const void* buf, const Geom& g,
+                             const float* inv_scale, const uint32_t* nodes, int count,
+                             double* out, hipStream_t stream);
+
+// rho [N] (nullable) and u [3][N] of F(t); sets *flag if a value is not finite.
+hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& g,
+                          const float* inv_scale, double* rho, double* u, int* flag,
+                          hipStream_t stream);
+
+// Plain streaming copy of n16 16-byte words.
+hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t stream);
+
+// Deterministic FP64 reductions over a velocity field u [3][N].
+//   kind 0: out[0..2] = sum_x u_a(x)
+//   kind 1: out[0]    = sum_x |u(x) - mean|^2     (mean = in[0..2] / N)
+//   kind 2: out[0]    = sum_x |curl_FD2 u(x)|^2
+// `partial` is device scratch of reduce_partials() doubles * 3.
+int reduce_partials();
+hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double* mean_sum,
+                         double* partial, double* out, hipStream_t stream);
+
+}  // namespace kbc

@@ -1,0 +1,544 @@
+// kbc_kernels.hip -- gfx950 kernels of the D3Q27 KBC lattice Boltzmann box:
+// the fused stream+collide step (pull and AA sweeps), initialisation at the
+// product-form equilibrium, layout conversion and FP64 diagnostics.
+//
+// Streaming follows f_i(x + v_i, t+1) = f'_i(x, t) on a periodic box
+// (section I, Eq. Egeneral); the collision is kbc::collide (section IV).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kbc_device.h"
+#include "kbc_internal.h"
+
+namespace kbc {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t n)
+{
+    // a in [0, n), d in {-1, 0, 1}
+    if (d > 0) return a + 1 == n ? 0u : a + 1;
+    if (d < 0) return a == 0 ? n - 1 : a - 1;
+    return a;
+}
+
+__device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, const Geom& g)
+{
+    return (z * g.ny + y) * g.nx + x;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step: one thread per node; 27 gathered loads, collision, 27 stores.
+//   pull:    read src[i][x - v_i], write dst[i][x]
+//   AA even: read buf[i][x],        write buf[26-i][x]
+//   AA odd:  read buf[26-i][x - v_i], write buf[i][x + v_i]
+// In both AA sweeps a node reads and writes the same 27 locations, so the
+// in-place update is free of races between nodes.
+// ---------------------------------------------------------------------------
+template <int S, int V, int SW>
+__global__ void __launch_bounds__(kBlock) k_step(StepParams p)
+{
+    using T = typename Traits<S>::T;
+    using R = typename Traits<S>::R;
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= p.g.nnodes) return;
+
+    uint32_t x, y, z;
+    node_xyz(n, p.g, x, y, z);
+    const uint32_t xm = x == 0 ? p.g.nx - 1 : x - 1, xp = x + 1 == p.g.nx ? 0 : x + 1;
+    const uint32_t ym = y == 0 ? p.g.ny - 1 : y - 1, yp = y + 1 == p.g.ny ? 0 : y + 1;
+    const uint32_t zm = z == 0 ? p.g.nz - 1 : z - 1, zp = z + 1 == p.g.nz ? 0 : z + 1;
+    // coordinate of x - v along each axis, indexed by v + 1
+    const uint32_t bx[3] = {xp, x, xm};
+    const uint32_t byo[3] = {yp * p.g.nx, y * p.g.nx, ym * p.g.nx};
+    const uint32_t bzo[3] = {zp * p.g.ny * p.g.nx, z * p.g.ny * p.g.nx, zm * p.g.ny * p.g.nx};
+    // coordinate of x + v
+    const uint32_t fx[3] = {xm, x, xp};
+    const uint32_t fyo[3] = {ym * p.g.nx, y * p.g.nx, yp * p.g.nx};
+    const uint32_t fzo[3] = {zm * p.g.ny * p.g.nx, z * p.g.ny * p.g.nx, zp * p.g.ny * p.g.nx};
+
+    const T* __restrict__ src = static_cast<const T*>(p.src);
+    T* __restrict__ dst = static_cast<T*>(p.dst);
+    const uint64_t plane = p.g.plane;
+
+    R f[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
+        if constexpr (SW == SW_PULL) {
+            f[i] = decode<S>(src[i * plane + (bzo[az] + byo[ay] + bx[ax])], p.inv_scale[i]);
+        } else if constexpr (SW == SW_AA_EVEN) {
+            f[i] = decode<S>(src[i * plane + n], p.inv_scale[i]);
+        } else {
+            f[i] = decode<S>(src[opp(i) * plane + (bzo[az] + byo[ay] + bx[ax])],
+                             p.inv_scale[opp(i)]);
+        }
+    }
+
+    collide<S, V>(f, p.c);
+
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
+        if constexpr (SW == SW_PULL) {
+            dst[i * plane + n] = encode<S>(f[i], p.scale[i]);
+        } else if constexpr (SW == SW_AA_EVEN) {
+            dst[opp(i) * plane + n] = encode<S>(f[i], p.scale[opp(i)]);
+        } else {
+            dst[i * plane + (fzo[az] + fyo[ay] + fx[ax])] = encode<S>(f[i], p.scale[i]);
+        }
+    }
+}
+
+using StepFn = void (*)(StepParams);
+
+template <int S, int V>
+constexpr StepFn step_fn(int sw)
+{
+    return sw == SW_PULL ? k_step<S, V, SW_PULL>
+                         : (sw == SW_AA_EVEN ? k_step<S, V, SW_AA_EVEN> : k_step<S, V, SW_AA_ODD>);
+}
+
+template <int S>
+StepFn step_fn_v(int v, int sw)
+{
+    switch (v) {
+    case V_D: return step_fn<S, V_D>(sw);
+    case V_DT: return step_fn<S, V_DT>(sw);
+    case V_DQ: return step_fn<S, V_DQ>(sw);
+    default: return step_fn<S, V_DTQ>(sw);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Storage location of canonical F_i(x) in a layout: (slot, node).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void locate(int layout, int i, uint32_t x, uint32_t y, uint32_t z,
+                                       const Geom& g, int& slot, uint32_t& node)
+{
+    const int vx = vel(i, 0), vy = vel(i, 1), vz = vel(i, 2);
+    if (layout == LY_PULL) {
+        slot = i;
+        node = node_of(wrap_add(x, vx, g.nx), wrap_add(y, vy, g.ny), wrap_add(z, vz, g.nz), g);
+    } else if (layout == LY_AA_EVEN) {
+        slot = i;
+        node = node_of(x, y, z, g);
+    } else {
+        slot = opp(i);
+        node = node_of(wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny), wrap_add(z, -vz, g.nz), g);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ double load_full(const void* buf, int slot, uint32_t node, int i,
+                                            const Geom& g, const float* inv_scale)
+{
+    using T = typename Traits<S>::T;
+    const T v = static_cast<const T*>(buf)[slot * g.plane + node];
+    if constexpr (S == ST_F64) return (double)v;
+    else if constexpr (S == ST_F32) return weight(i) + (double)v;
+    else return weight(i) + (double)((float)v * inv_scale[slot]);
+}
+
+template <int S>
+__device__ __forceinline__ void store_full(void* buf, int slot, uint32_t node, int i,
+                                           const Geom& g, const float* scale, double f)
+{
+    using T = typename Traits<S>::T;
+    T* b = static_cast<T*>(buf);
+    if constexpr (S == ST_F64) b[slot * g.plane + node] = f;
+    else if constexpr (S == ST_F32) b[slot * g.plane + node] = (float)(f - weight(i));
+    else b[slot * g.plane + node] = (_Float16)((float)(f - weight(i)) * scale[slot]);
+}
+
+// Product-form equilibrium of section II through its one-dimensional
+// marginals, in FP64: e_0 = (4 - 2S)/3, e_{+-1} = ((2S - 1)/3 +- u)/2.
+__device__ __forceinline__ void marginals(double u, double e[3])
+{
+    const double q3 = 3.0 * u * u;
+    const double sm1 = q3 / (1.0 + sqrt(1.0 + q3));
+    e[1] = 2.0 / 3.0 - (2.0 / 3.0) * sm1;
+    e[2] = 1.0 / 6.0 + sm1 / 3.0 + 0.5 * u;
+    e[0] = 1.0 / 6.0 + sm1 / 3.0 - 0.5 * u;
+}
+
+struct StoreCtx {
+    float scale[27];
+};
+
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_init_feq(int layout, void* buf, Geom g, StoreCtx sc,
+                                                     const double* __restrict__ u,
+                                                     const double* __restrict__ rho)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    uint32_t x, y, z;
+    node_xyz(n, g, x, y, z);
+    const double r = rho ? rho[n] : 1.0;
+    double ex[3], ey[3], ez[3];
+    marginals(u[n], ex);
+    marginals(u[g.nnodes + n], ey);
+    marginals(u[2 * (size_t)g.nnodes + n], ez);
+    for (int i = 0; i < 27; ++i) {
+        const double feq = r * ex[i % 3] * ey[(i / 3) % 3] * ez[i / 9];
+        int slot;
+        uint32_t node;
+        locate(layout, i, x, y, z, g, slot, node);
+        store_full<S>(buf, slot, node, i, g, sc.scale, feq);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_check_init(Geom g, const double* __restrict__ u,
+                                                       const double* __restrict__ rho, int* flag)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    bool bad = false;
+    for (int a = 0; a < 3; ++a) {
+        const double v = u[a * (size_t)g.nnodes + n];
+        bad |= !(fabs(v) < 1.0);
+    }
+    if (rho) bad |= !(rho[n] > 0.0 && isfinite(rho[n]));
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_feq_dev_max(Geom g, const double* __restrict__ u,
+                                                        const double* __restrict__ rho,
+                                                        unsigned* max_bits)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    const double r = rho ? rho[n] : 1.0;
+    double ex[3], ey[3], ez[3];
+    marginals(u[n], ex);
+    marginals(u[g.nnodes + n], ey);
+    marginals(u[2 * (size_t)g.nnodes + n], ez);
+    for (int i = 0; i < 27; ++i) {
+        const float d = (float)fabs(r * ex[i % 3] * ey[(i / 3) % 3] * ez[i / 9] - weight(i));
+        atomicMax(&max_bits[i], __float_as_uint(d));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pop_dev_max(Geom g, const double* __restrict__ f,
+                                                        unsigned* max_bits)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    for (int i = 0; i < 27; ++i) {
+        const float d = (float)fabs(f[i * (size_t)g.nnodes + n] - weight(i));
+        atomicMax(&max_bits[i], __float_as_uint(d));
+    }
+}
+
+struct LoadCtx {
+    float inv_scale[27];
+};
+
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_gather_pop(int layout, const void* buf, Geom g,
+                                                       LoadCtx lc, double* __restrict__ f)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    uint32_t x, y, z;
+    node_xyz(n, g, x, y, z);
+    for (int i = 0; i < 27; ++i) {
+        int slot;
+        uint32_t node;
+        locate(layout, i, x, y, z, g, slot, node);
+        f[i * (size_t)g.nnodes + n] = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_sample_pop(int layout, const void* buf, Geom g,
+                                                       LoadCtx lc, const uint32_t* __restrict__ nodes,
+                                                       int count, double* __restrict__ out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= count) return;
+    const uint32_t n = nodes[k];
+    uint32_t x, y, z;
+    node_xyz(n, g, x, y, z);
+    for (int i = 0; i < 27; ++i) {
+        int slot;
+        uint32_t node;
+        locate(layout, i, x, y, z, g, slot, node);
+        out[27 * (size_t)k + i] = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_scatter_pop(int layout, void* buf, Geom g, StoreCtx sc,
+                                                        const double* __restrict__ f)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    uint32_t x, y, z;
+    node_xyz(n, g, x, y, z);
+    for (int i = 0; i < 27; ++i) {
+        int slot;
+        uint32_t node;
+        locate(layout, i, x, y, z, g, slot, node);
+        store_full<S>(buf, slot, node, i, g, sc.scale, f[i * (size_t)g.nnodes + n]);
+    }
+}
+
+// rho = sum_i f_i, rho u = sum_i v_i f_i (section I), in FP64.  Deviation
+// forms sum the stored deviations and add the weights' share (1, 0).
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf, Geom g, LoadCtx lc,
+                                                    double* __restrict__ rho,
+                                                    double* __restrict__ u, int* flag)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    uint32_t x, y, z;
+    node_xyz(n, g, x, y, z);
+    double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        int slot;
+        uint32_t node;
+        locate(layout, i, x, y, z, g, slot, node);
+        double v = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+        if constexpr (S != ST_F64) v -= weight(i);
+        m += v;
+        jx += vel(i, 0) * v;
+        jy += vel(i, 1) * v;
+        jz += vel(i, 2) * v;
+    }
+    if constexpr (S != ST_F64) m += 1.0;
+    const double ir = 1.0 / m;
+    const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    if (rho) rho[n] = m;
+    u[n] = ux;
+    u[g.nnodes + n] = uy;
+    u[2 * (size_t)g.nnodes + n] = uz;
+    if (!(isfinite(m) && isfinite(ux) && isfinite(uy) && isfinite(uz))) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions: fixed grid, fixed per-thread order,
+// butterfly within the wavefront, fixed order across wavefronts and blocks.
+// ---------------------------------------------------------------------------
+constexpr int kReduceBlocks = 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_sum(double (&acc)[K], double* out)
+{
+    __shared__ double red[kBlock / 64][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += red[w][k];
+            out[k] = s;
+        }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock) k_reduce(Geom g, const double* __restrict__ u,
+                                                   const double* __restrict__ mean_sum,
+                                                   double* __restrict__ partial)
+{
+    const size_t N = g.nnodes;
+    double acc[3] = {0.0, 0.0, 0.0};
+    double mean[3] = {0.0, 0.0, 0.0};
+    if (KIND != 0)
+        for (int a = 0; a < 3; ++a) mean[a] = mean_sum[a] / (double)N;
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.nnodes; n += gridDim.x * kBlock) {
+        if (KIND == 0) {
+            for (int a = 0; a < 3; ++a) acc[a] += u[a * N + n];
+        } else if (KIND == 1) {
+            for (int a = 0; a < 3; ++a) {
+                const double d = u[a * N + n] - mean[a];
+                acc[0] += d * d;
+            }
+        } else {
+            uint32_t x, y, z;
+            node_xyz(n, g, x, y, z);
+            const uint32_t xp = node_of(wrap_add(x, 1, g.nx), y, z, g);
+            const uint32_t xm = node_of(wrap_add(x, -1, g.nx), y, z, g);
+            const uint32_t yp = node_of(x, wrap_add(y, 1, g.ny), z, g);
+            const uint32_t ym = node_of(x, wrap_add(y, -1, g.ny), z, g);
+            const uint32_t zp = node_of(x, y, wrap_add(z, 1, g.nz), g);
+            const uint32_t zm = node_of(x, y, wrap_add(z, -1, g.nz), g);
+            auto up = [&](int a, uint32_t m) { return u[a * N + m] - mean[a]; };
+            const double wx = 0.5 * (up(2, yp) - up(2, ym)) - 0.5 * (up(1, zp) - up(1, zm));
+            const double wy = 0.5 * (up(0, zp) - up(0, zm)) - 0.5 * (up(2, xp) - up(2, xm));
+            const double wz = 0.5 * (up(1, xp) - up(1, xm)) - 0.5 * (up(0, yp) - up(0, ym));
+            acc[0] += wx * wx + wy * wy + wz * wz;
+        }
+    }
+    block_sum<3>(acc, partial + 3 * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_final(const double* __restrict__ partial,
+                                                         int count, double* __restrict__ out)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < count; b += kBlock)
+        for (int k = 0; k < 3; ++k) acc[k] += partial[3 * b + k];
+    block_sum<3>(acc, out);
+}
+
+inline unsigned grid_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+
+__global__ void k_zero_u32(unsigned* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy16(uint4* __restrict__ dst,
+                                                  const uint4* __restrict__ src, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n16; k += stride)
+        dst[k] = src[k];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p, hipStream_t stream)
+{
+    StepFn fn;
+    switch (storage) {
+    case ST_F64: fn = step_fn_v<ST_F64>(variant, sweep); break;
+    case ST_F32: fn = step_fn_v<ST_F32>(variant, sweep); break;
+    default: fn = step_fn_v<ST_F16>(variant, sweep); break;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid_for(p.g.nnodes)), dim3(kBlock), 0, stream, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_feq(int storage, int layout, void* buf, const Geom& g, const float* scale,
+                           const double* u, const double* rho, hipStream_t stream)
+{
+    StoreCtx sc;
+    for (int i = 0; i < 27; ++i) sc.scale[i] = scale ? scale[i] : 1.0f;
+    const dim3 grid(grid_for(g.nnodes)), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL(k_init_feq<ST_F64>, grid, block, 0, stream, layout, buf, g, sc, u, rho);
+    else if (storage == ST_F32) hipLaunchKernelGGL(k_init_feq<ST_F32>, grid, block, 0, stream, layout, buf, g, sc, u, rho);
+    else hipLaunchKernelGGL(k_init_feq<ST_F16>, grid, block, 0, stream, layout, buf, g, sc, u, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_init(const Geom& g, const double* u, const double* rho, int* flag,
+                             hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_check_init, dim3(grid_for(g.nnodes)), dim3(kBlock), 0, stream, g, u, rho, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_feq_dev_max(const Geom& g, const double* u, const double* rho, unsigned* max_bits,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, max_bits, 27);
+    hipLaunchKernelGGL(k_feq_dev_max, dim3(grid_for(g.nnodes)), dim3(kBlock), 0, stream, g, u, rho, max_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_pop_dev_max(const Geom& g, const double* f, unsigned* max_bits, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, max_bits, 27);
+    hipLaunchKernelGGL(k_pop_dev_max, dim3(grid_for(g.nnodes)), dim3(kBlock), 0, stream, g, f, max_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_pop(int storage, int layout, const void* buf, const Geom& g,
+                             const float* inv_scale, double* f, hipStream_t stream)
+{
+    LoadCtx lc;
+    for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
+    const dim3 grid(grid_for(g.nnodes)), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL(k_gather_pop<ST_F64>, grid, block, 0, stream, layout, buf, g, lc, f);
+    else if (storage == ST_F32) hipLaunchKernelGGL(k_gather_pop<ST_F32>, grid, block, 0, stream, layout, buf, g, lc, f);
+    else hipLaunchKernelGGL(k_gather_pop<ST_F16>, grid, block, 0, stream, layout, buf, g, lc, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_pop(int storage, int layout, const void* buf, const Geom& g,
+                             const float* inv_scale, const uint32_t* nodes, int count,
+                             double* out, hipStream_t stream)
+{
+    LoadCtx lc;
+    for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
+    const dim3 grid((count + kBlock - 1) / kBlock), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL(k_sample_pop<ST_F64>, grid, block, 0, stream, layout, buf, g, lc, nodes, count, out);
+    else if (storage == ST_F32) hipLaunchKernelGGL(k_sample_pop<ST_F32>, grid, block, 0, stream, layout, buf, g, lc, nodes, count, out);
+    else hipLaunchKernelGGL(k_sample_pop<ST_F16>, grid, block, 0, stream, layout, buf, g, lc, nodes, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_pop(int storage, int layout, void* buf, const Geom& g, const float* scale,
+                              const double* f, hipStream_t stream)
+{
+    StoreCtx sc;
+    for (int i = 0; i < 27; ++i) sc.scale[i] = scale ? scale[i] : 1.0f;
+    const dim3 grid(grid_for(g.nnodes)), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL(k_scatter_pop<ST_F64>, grid, block, 0, stream, layout, buf, g, sc, f);
+    else if (storage == ST_F32) hipLaunchKernelGGL(k_scatter_pop<ST_F32>, grid, block, 0, stream, layout, buf, g, sc, f);
+    else hipLaunchKernelGGL(k_scatter_pop<ST_F16>, grid, block, 0, stream, layout, buf, g, sc, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& g,
+                          const float* inv_scale, double* rho, double* u, int* flag,
+                          hipStream_t stream)
+{
+    LoadCtx lc;
+    for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
+    const dim3 grid(grid_for(g.nnodes)), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL(k_moments<ST_F64>, grid, block, 0, stream, layout, buf, g, lc, rho, u, flag);
+    else if (storage == ST_F32) hipLaunchKernelGGL(k_moments<ST_F32>, grid, block, 0, stream, layout, buf, g, lc, rho, u, flag);
+    else hipLaunchKernelGGL(k_moments<ST_F16>, grid, block, 0, stream, layout, buf, g, lc, rho, u, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t stream)
+{
+    if (n16 == 0) return hipSuccess;
+    const size_t want = (n16 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)std::min<size_t>(want, 256 * 32);
+    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<uint4*>(dst),
+                       static_cast<const uint4*>(src), n16);
+    return hipGetLastError();
+}
+
+int reduce_partials() { return kReduceBlocks; }
+
+hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double* mean_sum,
+                         double* partial, double* out, hipStream_t stream)
+{
+    const unsigned blocks = std::min<unsigned>(kReduceBlocks, grid_for(g.nnodes));
+    if (kind == 0) hipLaunchKernelGGL(k_reduce<0>, dim3(blocks), dim3(kBlock), 0, stream, g, u, mean_sum, partial);
+    else if (kind == 1) hipLaunchKernelGGL(k_reduce<1>, dim3(blocks), dim3(kBlock), 0, stream, g, u, mean_sum, partial);
+    else hipLaunchKernelGGL(k_reduce<2>, dim3(blocks), dim3(kBlock), 0, stream, g, u, mean_sum, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace kbc

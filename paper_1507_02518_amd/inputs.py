@@ -64,45 +64,56 @@ def shear_wave(shape, U: float = 1e-3) -> np.ndarray:
 def hit(n, k0: float = 4.0, u_rms: float = 0.04, seed: int = 0) -> np.ndarray:
     """Random solenoidal field with shell spectrum ~ k^4 exp(-2 (k/k0)^2).
 
-    White Gaussian noise is transformed, projected onto the plane normal to
-    each wave vector, and every integer shell round(|k|) is rescaled so its
-    energy follows the target spectrum; the inverse transform is real because
-    all operations respect Hermitian symmetry.  The mean is removed and the
+    White Gaussian noise is transformed (real-to-complex, so Hermitian
+    symmetry holds by construction), projected onto the plane normal to each
+    wave vector, and every integer shell round(|k|) is rescaled so its
+    energy follows the target spectrum.  Nyquist planes of even-sized axes
+    (their own conjugate partners) are dropped.  The mean is removed and the
     field is scaled to the requested per-component r.m.s. value.
     """
+    import scipy.fft as sfft
+
     nx, ny, nz = _shape3(n)
     rng = np.random.default_rng(seed)
     w = rng.standard_normal((3, nz, ny, nx))
-    wh = np.fft.fftn(w, axes=(1, 2, 3))
+    wh = sfft.rfftn(w, axes=(1, 2, 3), workers=-1)
+    del w
     kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
     ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
-    kx = np.fft.fftfreq(nx, 1.0 / nx)[None, None, :]
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)[None, None, :]
     k2 = kx ** 2 + ky ** 2 + kz ** 2
-    kvec = np.stack(np.broadcast_arrays(kx, ky, kz)).astype(np.float64)
     k2s = np.where(k2 == 0, 1.0, k2)
-    kdotw = (kvec * wh).sum(axis=0)
-    wh = wh - kvec * kdotw / k2s
-    wh[:, k2 == 0] = 0.0
-    # the Nyquist planes of an even-sized grid are their own conjugate
-    # partners, where the projection cannot stay Hermitian: drop them
-    nyq = np.zeros(k2.shape, dtype=bool)
-    for kv, n_ in ((kx, nx), (ky, ny), (kz, nz)):
-        if n_ % 2 == 0:
-            nyq |= np.broadcast_to(np.abs(kv) == n_ // 2, k2.shape)
-    wh[:, nyq] = 0.0
-    kmag = np.sqrt(k2)
-    shell = np.rint(kmag).astype(np.int64)
-    e_now = np.bincount(shell.ravel(), weights=(np.abs(wh) ** 2).sum(axis=0).ravel())
+    kdotw = (kx * wh[0] + ky * wh[1] + kz * wh[2]) / k2s
+    wh[0] -= kx * kdotw
+    wh[1] -= ky * kdotw
+    wh[2] -= kz * kdotw
+    del kdotw
+    drop = k2 == 0
+    if nx % 2 == 0:
+        drop = drop | (kx == nx // 2)
+    if ny % 2 == 0:
+        drop = drop | (np.abs(ky) == ny // 2)
+    if nz % 2 == 0:
+        drop = drop | (np.abs(kz) == nz // 2)
+    wh[:, drop] = 0.0
+    # modes with 0 < kx < nx/2 stand for themselves and their conjugates
+    mult = np.where((kx == 0) | ((nx % 2 == 0) & (kx == nx // 2)), 1.0, 2.0)
+    mult = np.broadcast_to(mult, k2.shape)
+    shell = np.rint(np.sqrt(k2)).astype(np.int64)
+    e_now = np.bincount(shell.ravel(),
+                        weights=(mult * (np.abs(wh) ** 2).sum(axis=0)).ravel())
     kk = np.arange(e_now.size, dtype=np.float64)
     e_target = kk ** 4 * np.exp(-2.0 * (kk / k0) ** 2)
     scale = np.zeros_like(e_now)
     ok = e_now > 0
     scale[ok] = np.sqrt(e_target[ok] / e_now[ok])
-    wh = wh * scale[shell][None]
-    u = np.real(np.fft.ifftn(wh, axes=(1, 2, 3)))
+    wh *= scale[shell][None]
+    u = sfft.irfftn(wh, s=(nz, ny, nx), axes=(1, 2, 3), workers=-1)
+    del wh
     u -= u.mean(axis=(1, 2, 3), keepdims=True)
     rms = np.sqrt((u ** 2).sum(axis=0).mean() / 3.0)
-    return np.ascontiguousarray(u * (u_rms / rms))
+    u *= u_rms / rms
+    return np.ascontiguousarray(u)
 
 
 def smooth_random(shape, amplitude: float = 0.03, modes: int = 4, seed: int = 0) -> np.ndarray:

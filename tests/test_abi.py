@@ -1,0 +1,122 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, its ctypes mirror matches the C layout, argument errors come back
+as codes without touching a GPU, and the host-side index math is exact."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1507_02518_amd import kbc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kbc.h")
+CSRC = os.path.join(ROOT, "paper_1507_02518_amd", "csrc")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kbc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = kbc.load()
+    names = _declared()
+    assert "kbc_create" in names and "kbc_step" in names and "kbc_energy" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", kbc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def test_options_struct_layout_matches_header():
+    src = r"""
+    #include <stddef.h>
+    #include <stdio.h>
+    #include "kbc.h"
+    int main(void) {
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kbc_options),
+             offsetof(kbc_options, variant), offsetof(kbc_options, streaming),
+             offsetof(kbc_options, gamma_fixed), offsetof(kbc_options, device),
+             offsetof(kbc_options, gamma_value), offsetof(kbc_options, gamma_eps),
+             offsetof(kbc_options, stream));
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split()]
+    O = kbc.kbc_options
+    want = [ctypes.sizeof(O)] + [getattr(O, f).offset for f in
+                                 ("variant", "streaming", "gamma_fixed", "device",
+                                  "gamma_value", "gamma_eps", "stream")]
+    assert vals == want
+
+
+def test_options_defaults():
+    o = kbc.kbc_options_default()
+    assert o.variant == kbc.S_DTQ and o.streaming == kbc.PULL
+    assert o.gamma_fixed == 0 and o.device == -1 and not o.stream
+
+
+@pytest.mark.parametrize("shape,nu,dtype", [
+    ((0, 4, 4), 1e-3, kbc.F64),
+    ((4, -1, 4), 1e-3, kbc.F64),
+    ((4, 4, 4), 0.0, kbc.F64),
+    ((4, 4, 4), -1e-3, kbc.F64),
+    ((4, 4, 4), float("nan"), kbc.F64),
+    ((4, 4, 4), 1e-3, 7),
+    ((2048, 1024, 1024), 1e-3, kbc.F64),
+])
+def test_create_rejects_bad_arguments(shape, nu, dtype):
+    with pytest.raises(kbc.KbcError) as e:
+        kbc.kbc_create(shape, nu, dtype)
+    assert e.value.code == kbc.KBC_EINVAL
+    assert kbc.kbc_last_error()
+
+
+def test_create_rejects_bad_options():
+    o = kbc.kbc_options_default()
+    o.variant = 9
+    with pytest.raises(kbc.KbcError) as e:
+        kbc.kbc_create((4, 4, 4), 1e-3, kbc.F64, o)
+    assert e.value.code == kbc.KBC_EINVAL
+    o = kbc.kbc_options_default()
+    o.streaming = 5
+    with pytest.raises(kbc.KbcError):
+        kbc.kbc_create((4, 4, 4), 1e-3, kbc.F64, o)
+
+
+def test_null_handles_are_rejected():
+    lib = kbc.load()
+    assert lib.kbc_destroy(None) == kbc.KBC_OK
+    assert lib.kbc_step(None, 1) == kbc.KBC_EINVAL
+    k = ctypes.c_double()
+    assert lib.kbc_energy(None, ctypes.byref(k)) == kbc.KBC_EINVAL
+    assert lib.kbc_sync(None) == kbc.KBC_EINVAL
+    assert lib.kbc_moments(None, None, None) == kbc.KBC_EINVAL
+    assert b"null handle" in lib.kbc_last_error()
+
+
+def test_fast_division_host_check():
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("ROCm clang++ not present")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "fd")
+        subprocess.run([clang, "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__",
+                        "-I/opt/rocm/include", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host", "fastdiv_check.cpp"), "-o", exe],
+                       check=True)
+        r = subprocess.run([exe], capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
