@@ -70,8 +70,9 @@ def read_counters():
         return None
 
 
-def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup):
-    stream = torch.cuda.current_stream()
+def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream):
+    # the box enqueues on `stream` (a torch stream of default priority); the
+    # events are recorded on the same stream, so they bracket the launches
     with kbc.Box(N, NU, dtype, streaming=streaming, stream=stream.cuda_stream) as box:
         kbc.kbc_init_velocity_device(box.h, u_dev.data_ptr(), None)
         box.step(warmup)
@@ -94,12 +95,11 @@ def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup):
             "wall_s": wall, "energy_after": k}
 
 
-def copy_ceiling(kbc, torch):
+def copy_ceiling(kbc, torch, stream):
     """Achievable HBM bandwidth of a plain streaming copy (2 x 2 GiB)."""
     nbytes = 2 << 30
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
     for _ in range(3):
         kbc.kbc_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     args = ap.parse_args()
@@ -154,9 +154,12 @@ def main():
     log(f"[bench] building the 256^3 HIT field (seed {SEED})")
     u = inputs.hit(N, K0, URMS, seed=SEED)
     u_dev = torch.from_numpy(u).cuda()
+    stream = torch.cuda.Stream()
+    assert stream.cuda_stream, "need a non-null stream"
+    torch.cuda.synchronize()
 
     log("[bench] FP64 pull (headline)")
-    head = time_form(kbc, torch, u_dev, kbc.F64, kbc.PULL, args.steps, args.warmup)
+    head = time_form(kbc, torch, u_dev, kbc.F64, kbc.PULL, args.steps, args.warmup, stream)
     log(f"[bench]   {head['mlups']:.0f} MLUPS, {head['algorithmic_GBs']:.0f} GB/s")
 
     forms = {}
@@ -164,11 +167,11 @@ def main():
         for name, dt, st in [("f64_aa", kbc.F64, kbc.AA), ("f32dev_pull", kbc.F32_DEV, kbc.PULL),
                              ("f32dev_aa", kbc.F32_DEV, kbc.AA), ("f16dev_aa", kbc.F16_DEV, kbc.AA)]:
             log(f"[bench] {name}")
-            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup)
+            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup, stream)
             forms[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
     log("[bench] copy ceiling")
-    copy_gbs = copy_ceiling(kbc, torch)
+    copy_gbs = copy_ceiling(kbc, torch, stream)
     del u_dev
     torch.cuda.empty_cache()
 

@@ -140,7 +140,7 @@ __device__ __forceinline__ typename Traits<S>::T encode(typename Traits<S>::R v,
 //  7. f' = f - beta (2 ds + gamma dh).
 // ---------------------------------------------------------------------------
 template <int S, int V>
-__device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
+__host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
 {
     using R = typename Traits<S>::R;
     constexpr bool DEV = Traits<S>::kDev;

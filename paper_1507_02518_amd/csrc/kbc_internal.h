@@ -11,7 +11,7 @@ namespace kbc {
 
 // Population storage layout of one box (all modes are [27][nz][ny][nx]):
 //   pull:  buffer `cur` holds the post-collision P(t-1) so that
-//          F_i(x, t) = cur[i][x - v_i];
+//          F_i(x, t) = cur[i][x - v_i] (at t = 0, cur[i][x] = f^eq_i(x + v_i));
 //   AA:    even t: F_i(x, t) = buf[i][x]; odd t: F_i(x, t) = buf[26-i][x - v_i].
 enum Layout : int { LY_PULL = 0, LY_AA_EVEN = 1, LY_AA_ODD = 2 };
 

@@ -120,8 +120,9 @@ __device__ __forceinline__ void locate(int layout, int i, uint32_t x, uint32_t y
 {
     const int vx = vel(i, 0), vy = vel(i, 1), vz = vel(i, 2);
     if (layout == LY_PULL) {
+        // the pull sweep reads F_i(x) from the post-collision buffer at x - v_i
         slot = i;
-        node = node_of(wrap_add(x, vx, g.nx), wrap_add(y, vy, g.ny), wrap_add(z, vz, g.nz), g);
+        node = node_of(wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny), wrap_add(z, -vz, g.nz), g);
     } else if (layout == LY_AA_EVEN) {
         slot = i;
         node = node_of(x, y, z, g);
@@ -205,32 +206,49 @@ __global__ void __launch_bounds__(kBlock) k_check_init(Geom g, const double* __r
     if (bad) atomicOr(flag, 1);
 }
 
+// Per-direction maximum over the block first (non-negative floats compare
+// like their bit patterns), then one atomic per direction and block.
+__device__ __forceinline__ void block_max_27(float (&d)[27], unsigned* max_bits)
+{
+    __shared__ unsigned red[27];
+    if (threadIdx.x < 27) red[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = 0; i < 27; ++i) {
+        unsigned v = __float_as_uint(d[i]);
+        for (int off = 32; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(&red[i], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) atomicMax(&max_bits[threadIdx.x], red[threadIdx.x]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_feq_dev_max(Geom g, const double* __restrict__ u,
                                                         const double* __restrict__ rho,
                                                         unsigned* max_bits)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.nnodes) return;
-    const double r = rho ? rho[n] : 1.0;
-    double ex[3], ey[3], ez[3];
-    marginals(u[n], ex);
-    marginals(u[g.nnodes + n], ey);
-    marginals(u[2 * (size_t)g.nnodes + n], ez);
-    for (int i = 0; i < 27; ++i) {
-        const float d = (float)fabs(r * ex[i % 3] * ey[(i / 3) % 3] * ez[i / 9] - weight(i));
-        atomicMax(&max_bits[i], __float_as_uint(d));
+    float d[27];
+    for (int i = 0; i < 27; ++i) d[i] = 0.0f;
+    if (n < g.nnodes) {
+        const double r = rho ? rho[n] : 1.0;
+        double ex[3], ey[3], ez[3];
+        marginals(u[n], ex);
+        marginals(u[g.nnodes + n], ey);
+        marginals(u[2 * (size_t)g.nnodes + n], ez);
+        for (int i = 0; i < 27; ++i)
+            d[i] = (float)fabs(r * ex[i % 3] * ey[(i / 3) % 3] * ez[i / 9] - weight(i));
     }
+    block_max_27(d, max_bits);
 }
 
 __global__ void __launch_bounds__(kBlock) k_pop_dev_max(Geom g, const double* __restrict__ f,
                                                         unsigned* max_bits)
 {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.nnodes) return;
-    for (int i = 0; i < 27; ++i) {
-        const float d = (float)fabs(f[i * (size_t)g.nnodes + n] - weight(i));
-        atomicMax(&max_bits[i], __float_as_uint(d));
-    }
+    float d[27];
+    for (int i = 0; i < 27; ++i)
+        d[i] = n < g.nnodes ? (float)fabs(f[i * (size_t)g.nnodes + n] - weight(i)) : 0.0f;
+    block_max_27(d, max_bits);
 }
 
 struct LoadCtx {
@@ -407,12 +425,28 @@ __global__ void k_zero_u32(unsigned* p, int n)
     if (i < n) p[i] = 0u;
 }
 
-__global__ void __launch_bounds__(kBlock) k_copy16(uint4* __restrict__ dst,
-                                                  const uint4* __restrict__ src, size_t n16)
+// Streaming copy: each thread moves four 16-byte words per iteration, the
+// four loads issued before the stores; the grid covers the array once when
+// it can (one block per 16 KiB).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
+                                                  const u32x4* __restrict__ src, size_t n16)
 {
-    const size_t stride = (size_t)gridDim.x * kBlock;
-    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n16; k += stride)
-        dst[k] = src[k];
+    const size_t stride = (size_t)gridDim.x * kBlock * 4;
+    for (size_t base = (size_t)blockIdx.x * kBlock * 4 + threadIdx.x; base < n16; base += stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t k = base + (size_t)j * kBlock;
+            if (k < n16) v[j] = __builtin_nontemporal_load(&src[k]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t k = base + (size_t)j * kBlock;
+            if (k < n16) __builtin_nontemporal_store(v[j], &dst[k]);
+        }
+    }
 }
 
 }  // namespace
@@ -519,10 +553,10 @@ hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& 
 hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t stream)
 {
     if (n16 == 0) return hipSuccess;
-    const size_t want = (n16 + kBlock - 1) / kBlock;
-    const unsigned blocks = (unsigned)std::min<size_t>(want, 256 * 32);
-    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<uint4*>(dst),
-                       static_cast<const uint4*>(src), n16);
+    const size_t want = (n16 + 4 * kBlock - 1) / (4 * kBlock);
+    const unsigned blocks = (unsigned)std::min<size_t>(want, 1u << 20);
+    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<u32x4*>(dst),
+                       static_cast<const u32x4*>(src), n16);
     return hipGetLastError();
 }
 
