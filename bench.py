@@ -164,8 +164,12 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        for name, dt, st in [("f64_aa", kbc.F64, kbc.AA), ("f32dev_pull", kbc.F32_DEV, kbc.PULL),
-                             ("f32dev_aa", kbc.F32_DEV, kbc.AA), ("f16dev_aa", kbc.F16_DEV, kbc.AA)]:
+        for name, dt, st in [("f64_aa", kbc.F64, kbc.AA),
+                             ("f32dev_pull", kbc.F32_DEV, kbc.PULL),
+                             ("f32dev_aa", kbc.F32_DEV, kbc.AA),
+                             ("f32devx_pull", kbc.F32_DEV_X, kbc.PULL),
+                             ("f32devx_aa", kbc.F32_DEV_X, kbc.AA),
+                             ("f16dev_aa", kbc.F16_DEV, kbc.AA)]:
             log(f"[bench] {name}")
             r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup, stream)
             forms[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}

@@ -52,10 +52,13 @@ extern "C" {
 #define KBC_ESTATE (-6)     /* call not valid in the current state */
 
 /* Storage precision of the populations.  KBC_F64 stores f_i in FP64 and
- * collides in FP64.  The two deviation forms store f_i - W_i (FP32, or FP16
- * times a per-direction power-of-two scale fixed at initialisation) and
- * collide in FP32. */
-typedef enum { KBC_F64 = 0, KBC_F32_DEV = 1, KBC_F16_DEV = 2 } kbc_dtype;
+ * collides in FP64.  The deviation forms store f_i - W_i (FP32, or FP16 times
+ * a per-direction power-of-two scale fixed at initialisation) and collide in
+ * FP32.  KBC_F32_DEV_X stores like KBC_F32_DEV but forms rho, u and
+ * f_i - f_i^eq in FP64 before the FP32 collision, which removes the
+ * cancellation error of the pure FP32 collision (4 bytes per population
+ * either way). */
+typedef enum { KBC_F64 = 0, KBC_F32_DEV = 1, KBC_F16_DEV = 2, KBC_F32_DEV_X = 3 } kbc_dtype;
 
 /* Shear part s of the natural-moment KBC models (section IV):
  * s = d, d+t, d+q or d+t+q.  The paper's simulations use d+t+q. */

@@ -41,7 +41,7 @@ int hip_fail(hipError_t e, const char* where)
 
 size_t elem_bytes(int dtype)
 {
-    return dtype == KBC_F64 ? 8 : (dtype == KBC_F32_DEV ? 4 : 2);
+    return dtype == KBC_F64 ? 8 : (dtype == KBC_F16_DEV ? 2 : 4);
 }
 
 }  // namespace
@@ -175,7 +175,7 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     const double nn = (double)shape[0] * (double)shape[1] * (double)shape[2];
     if (nn >= 2147483648.0) return fail(KBC_EINVAL, "box has 2^31 nodes or more");
     if (!(nu > 0.0) || !std::isfinite(nu)) return fail(KBC_EINVAL, "nu must be finite and > 0");
-    if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV)
+    if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV && dtype != KBC_F32_DEV_X)
         return fail(KBC_EINVAL, "unknown dtype");
     if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return fail(KBC_EINVAL, "unknown variant");
     if (opt.streaming != KBC_PULL && opt.streaming != KBC_AA) return fail(KBC_EINVAL, "unknown streaming");

@@ -9,7 +9,7 @@
 
 namespace kbc {
 
-enum Storage : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
+enum Storage : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_F32X = 3 };
 enum Variant : int { V_D = 0, V_DT = 1, V_DQ = 2, V_DTQ = 3 };
 enum Sweep : int { SW_PULL = 0, SW_AA_EVEN = 1, SW_AA_ODD = 2 };
 
@@ -98,16 +98,27 @@ template <> struct Traits<ST_F64> {
     using T = double;
     using R = double;
     static constexpr bool kDev = false;
+    static constexpr bool kMixed = false;
 };
 template <> struct Traits<ST_F32> {
     using T = float;
     using R = float;
     static constexpr bool kDev = true;
+    static constexpr bool kMixed = false;
 };
 template <> struct Traits<ST_F16> {
     using T = _Float16;
     using R = float;
     static constexpr bool kDev = true;
+    static constexpr bool kMixed = false;
+};
+// FP32 deviation storage; the conserved moments and f - f^eq are formed in
+// FP64 (they are differences of O(u) quantities), the rest in FP32.
+template <> struct Traits<ST_F32X> {
+    using T = float;
+    using R = float;
+    static constexpr bool kDev = true;
+    static constexpr bool kMixed = true;
 };
 
 template <int S>
@@ -132,27 +143,23 @@ __device__ __forceinline__ typename Traits<S>::T encode(typename Traits<S>::R v,
 //     product-form factors of section II reduce to e_0 = (4 - 2S)/3,
 //     e_{+-1} = ((2S - 1)/3 +- u)/2 per axis, f_i^eq = rho e(vx) e(vy) e(vz);
 //  3-4. ds from the differences of the 13 second- and third-order natural
-//     moments of f and f^eq (table s_parts); the equilibrium moments factor
-//     as rho m_p(u_x) m_q(u_y) m_r(u_z), m_0 = 1, m_1 = u, m_2 = (2S - 1)/3;
+//     moments of f and f^eq (table s_parts);
 //  5. dh = f - f^eq - ds;
 //  6. gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, 1/f^eq_i separable;
 //     gamma = 2 where <dh|dh> <= gamma_eps * rho (0/0 at equilibrium);
 //  7. f' = f - beta (2 ds + gamma dh).
 // ---------------------------------------------------------------------------
-template <int S, int V>
-__host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
-{
-    using R = typename Traits<S>::R;
-    constexpr bool DEV = Traits<S>::kDev;
-    constexpr bool WT = (V == V_DT || V == V_DTQ);
-    constexpr bool WQ = (V == V_DQ || V == V_DTQ);
-    const R third = R(1.0 / 3.0);
 
-    // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ------
+// Separable moment transform along x, then y, then z: for each line of three
+// populations (v = -1, 0, +1) the sums m0 = f- + f0 + f+, m1 = f+ - f-,
+// m2 = f+ + f-.  M[p][q][r] = sum_i g_i vx^p vy^q vz^r.
+template <typename R>
+__host__ __device__ __forceinline__ void moments27(const R (&g)[27], R (&M)[3][3][3])
+{
     R X[3][9];
 #pragma unroll
     for (int yz = 0; yz < 9; ++yz) {
-        const R fm = f[3 * yz + 0], f0 = f[3 * yz + 1], fp = f[3 * yz + 2];
+        const R fm = g[3 * yz + 0], f0 = g[3 * yz + 1], fp = g[3 * yz + 2];
         const R s2 = fp + fm;
         X[0][yz] = s2 + f0;
         X[1][yz] = fp - fm;
@@ -169,7 +176,6 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             Y[p][1][az] = d - a;
             Y[p][2][az] = s2;
         }
-    R M[3][3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
@@ -180,77 +186,68 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             M[p][q][1] = d - a;
             M[p][q][2] = s2;
         }
+}
 
-    // rho and u (deviation forms: rho = 1 + sum g, sum v W = 0)
-    const R drho = DEV ? M[0][0][0] : M[0][0][0] - R(1);
-    const R rho = DEV ? R(1) + drho : M[0][0][0];
-    const R irho = R(1) / rho;
-    const R u[3] = {M[1][0][0] * irho, M[0][1][0] * irho, M[0][0][1] * irho};
+// Differences of the named moments of section III between f and f^eq.
+template <typename R>
+struct DMom {
+    R T, Nxz, Nyz, Pxy, Pxz, Pyz, Qxyy, Qxzz, Qxxy, Qyzz, Qxxz, Qyyz, Qxyz;
+};
 
-    // --- 2. one-dimensional equilibrium marginals --------------------------
-    R E[3][3], dE[3][3], m2[3], dm2[3], iE[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const R ua = u[a];
-        const R q3 = R(3) * ua * ua;
-        const R Sq = sqrt(R(1) + q3);
-        R sm1;  // S - 1, formed without cancellation in the FP32 forms
-        if constexpr (DEV) sm1 = q3 / (R(1) + Sq);
-        else sm1 = Sq - R(1);
-        dm2[a] = R(2.0 / 3.0) * sm1;
-        m2[a] = third + dm2[a];
-        const R half_u = R(0.5) * ua;
-        dE[a][1] = -dm2[a];
-        dE[a][2] = R(0.5) * dm2[a] + half_u;
-        dE[a][0] = R(0.5) * dm2[a] - half_u;
-        E[a][1] = R(2.0 / 3.0) + dE[a][1];
-        E[a][2] = R(1.0 / 6.0) + dE[a][2];
-        E[a][0] = R(1.0 / 6.0) + dE[a][0];
-        // three reciprocals from one division
-        const R pm = E[a][0] * E[a][2];
-        const R ip = R(1) / (pm * E[a][1]);
-        iE[a][1] = pm * ip;
-        iE[a][2] = E[a][1] * E[a][0] * ip;
-        iE[a][0] = E[a][1] * E[a][2] * ip;
-    }
+// One-dimensional equilibrium marginals of one axis (section II, product
+// form): e[v+1] and de[v+1] = e - W_v, plus m2 - 1/3 where m2 = (2S - 1)/3.
+template <typename R, bool kNoCancel>
+__host__ __device__ __forceinline__ void marginals1d(R u, R (&e)[3], R (&de)[3], R& dm2)
+{
+    const R q3 = R(3) * u * u;
+    const R Sq = sqrt(R(1) + q3);
+    R sm1;  // S - 1, without cancellation where asked
+    if constexpr (kNoCancel) sm1 = q3 / (R(1) + Sq);
+    else sm1 = Sq - R(1);
+    dm2 = R(2.0 / 3.0) * sm1;
+    const R half_u = R(0.5) * u;
+    de[1] = -dm2;
+    de[2] = R(0.5) * dm2 + half_u;
+    de[0] = R(0.5) * dm2 - half_u;
+    e[1] = R(2.0 / 3.0) + de[1];
+    e[2] = R(1.0 / 6.0) + de[2];
+    e[0] = R(1.0 / 6.0) + de[0];
+}
 
-    // --- 3-4. moment differences and the shear part per direction class ----
-    // second-order diagonal moments carry the weights' share 1/3 (deviation
-    // forms) and rho m_2 = (1 + drho)(1/3 + dm_2)
-    R dD[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const R Mdiag = a == 0 ? M[2][0][0] : (a == 1 ? M[0][2][0] : M[0][0][2]);
-        if constexpr (DEV) dD[a] = Mdiag - (drho * third + rho * dm2[a]);
-        else dD[a] = Mdiag - rho * m2[a];
-    }
-    const R dT = dD[0] + dD[1] + dD[2];
-    const R dNxz = dD[0] - dD[2];
-    const R dNyz = dD[1] - dD[2];
-    const R dPxy = M[1][1][0] - rho * u[0] * u[1];
-    const R dPxz = M[1][0][1] - rho * u[0] * u[2];
-    const R dPyz = M[0][1][1] - rho * u[1] * u[2];
-    const R dQxyy = M[1][2][0] - rho * u[0] * m2[1];
-    const R dQxzz = M[1][0][2] - rho * u[0] * m2[2];
-    const R dQxxy = M[2][1][0] - rho * m2[0] * u[1];
-    const R dQyzz = M[0][1][2] - rho * u[1] * m2[2];
-    const R dQxxz = M[2][0][1] - rho * m2[0] * u[2];
-    const R dQyyz = M[0][2][1] - rho * m2[1] * u[2];
-    const R dQxyz = M[1][1][1] - rho * u[0] * u[1] * u[2];
+// 1/e for the three marginal values of one axis from a single division.
+template <typename R>
+__host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
+{
+    const R pm = e[0] * e[2];
+    const R ip = R(1) / (pm * e[1]);
+    ie[1] = pm * ip;
+    ie[2] = e[1] * e[0] * ip;
+    ie[0] = e[1] * e[2] * ip;
+}
 
-    const R t6 = WT ? dT * R(1.0 / 6.0) : R(0);
-    const R sRest = WT ? -dT : R(0);
-    const R sF[3] = {(R(2) * dNxz - dNyz) * R(1.0 / 6.0) + t6,
-                     (R(2) * dNyz - dNxz) * R(1.0 / 6.0) + t6,
-                     -(dNxz + dNyz) * R(1.0 / 6.0) + t6};
-    const R qF[3] = {WQ ? R(-0.5) * (dQxyy + dQxzz) : R(0),
-                     WQ ? R(-0.5) * (dQxxy + dQyzz) : R(0),
-                     WQ ? R(-0.5) * (dQxxz + dQyyz) : R(0)};
-    const R eXY = R(0.25) * dPxy, eXZ = R(0.25) * dPxz, eYZ = R(0.25) * dPyz;
-    const R qXYy = WQ ? R(0.25) * dQxxy : R(0), qXYx = WQ ? R(0.25) * dQxyy : R(0);
-    const R qXZz = WQ ? R(0.25) * dQxxz : R(0), qXZx = WQ ? R(0.25) * dQxzz : R(0);
-    const R qYZz = WQ ? R(0.25) * dQyyz : R(0), qYZy = WQ ? R(0.25) * dQyzz : R(0);
-    const R qC = WQ ? R(0.125) * dQxyz : R(0);
+// Steps 3-7 given the moment differences, f - f^eq (fneq_of(i)) and the
+// separable 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].
+template <typename R, int V, typename FneqFn>
+__host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d, FneqFn fneq_of,
+                                                   const R (&iCx)[3], const R (&iA9)[9],
+                                                   double rho, const Coll& c)
+{
+    constexpr bool WT = (V == V_DT || V == V_DTQ);
+    constexpr bool WQ = (V == V_DQ || V == V_DTQ);
+    // table s_parts: value of ds per direction class
+    const R t6 = WT ? d.T * R(1.0 / 6.0) : R(0);
+    const R sRest = WT ? -d.T : R(0);
+    const R sF[3] = {(R(2) * d.Nxz - d.Nyz) * R(1.0 / 6.0) + t6,
+                     (R(2) * d.Nyz - d.Nxz) * R(1.0 / 6.0) + t6,
+                     -(d.Nxz + d.Nyz) * R(1.0 / 6.0) + t6};
+    const R qF[3] = {WQ ? R(-0.5) * (d.Qxyy + d.Qxzz) : R(0),
+                     WQ ? R(-0.5) * (d.Qxxy + d.Qyzz) : R(0),
+                     WQ ? R(-0.5) * (d.Qxxz + d.Qyyz) : R(0)};
+    const R eXY = R(0.25) * d.Pxy, eXZ = R(0.25) * d.Pxz, eYZ = R(0.25) * d.Pyz;
+    const R qXYy = WQ ? R(0.25) * d.Qxxy : R(0), qXYx = WQ ? R(0.25) * d.Qxyy : R(0);
+    const R qXZz = WQ ? R(0.25) * d.Qxxz : R(0), qXZx = WQ ? R(0.25) * d.Qxzz : R(0);
+    const R qYZz = WQ ? R(0.25) * d.Qyyz : R(0), qYZy = WQ ? R(0.25) * d.Qyzz : R(0);
+    const R qC = WQ ? R(0.125) * d.Qxyz : R(0);
 
     auto ds_of = [&](int i) -> R {
         const int sx = vel(i, 0), sy = vel(i, 1), sz = vel(i, 2);
@@ -269,30 +266,6 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         return R(sx * sy * sz) * qC;
     };
 
-    // equilibrium (or its deviation from W) and 1/f^eq, from the marginals
-    R A9[9], B9[9], iA9[9];
-#pragma unroll
-    for (int yz = 0; yz < 9; ++yz) {
-        const int ay = yz % 3, az = yz / 3;
-        A9[yz] = E[1][ay] * E[2][az];
-        iA9[yz] = iE[1][ay] * iE[2][az];
-        if constexpr (DEV) B9[yz] = dE[1][ay] * E[2][az] + R(w1(ay - 1)) * dE[2][az];
-        else B9[yz] = R(0);
-    }
-    R Cx[3], iCx[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if constexpr (DEV) Cx[ax] = dE[0][ax] + drho * E[0][ax];
-        else Cx[ax] = rho * E[0][ax];
-        iCx[ax] = irho * iE[0][ax];
-    }
-    // f_i - f_i^eq
-    auto fneq_of = [&](int i) -> R {
-        const int ax = i % 3, yz = i / 3;
-        if constexpr (DEV) return f[i] - (A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
-        else return f[i] - A9[yz] * Cx[ax];
-    };
-
     // --- 5-6. dh and the entropic scalar products --------------------------
     R sh = R(0), hh = R(0);
 #pragma unroll
@@ -309,7 +282,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
     } else {
         // ratio and fallback test in FP64 for every storage form
         const double hhd = (double)hh, shd = (double)sh;
-        gamma = (hhd <= c.gamma_eps * (double)rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
+        gamma = (hhd <= c.gamma_eps * rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
     }
 
     // --- 7. relax: f' = f - beta (2 ds + gamma dh) -------------------------
@@ -319,6 +292,152 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         const R ds = ds_of(i);
         const R dh = fneq_of(i) - ds;
         f[i] = f[i] - beta * (R(2) * ds + gamma * dh);
+    }
+}
+
+template <int S, int V>
+__host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
+{
+    using R = typename Traits<S>::R;
+    constexpr bool DEV = Traits<S>::kDev;
+
+    if constexpr (Traits<S>::kMixed) {
+        // --- 1-2 in FP64: rho, u and f - f^eq from the deviations g --------
+        double X0[9], X1[9];
+#pragma unroll
+        for (int yz = 0; yz < 9; ++yz) {
+            const double fm = f[3 * yz + 0], f0 = f[3 * yz + 1], fp = f[3 * yz + 2];
+            X0[yz] = (fm + f0) + fp;
+            X1[yz] = fp - fm;
+        }
+        double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int yz = 0; yz < 9; ++yz) {
+            const int vy = yz % 3 - 1, vz = yz / 3 - 1;
+            drho += X0[yz];
+            jx += X1[yz];
+            if (vy) jy += vy * X0[yz];
+            if (vz) jz += vz * X0[yz];
+        }
+        const double rho = 1.0 + drho;
+        const double irho = 1.0 / rho;
+        const double u[3] = {jx * irho, jy * irho, jz * irho};
+        double E[3][3], dE[3][3], dm2;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) marginals1d<double, true>(u[a], E[a], dE[a], dm2);
+        // f_i - f_i^eq = g_i - (rho e_x e_y e_z - W_x W_y W_z), expanded so
+        // that no O(1) terms cancel
+        R fneq[27];
+#pragma unroll
+        for (int yz = 0; yz < 9; ++yz) {
+            const int ay = yz % 3, az = yz / 3;
+            const double A = E[1][ay] * E[2][az];
+            const double B = dE[1][ay] * E[2][az] + w1(ay - 1) * dE[2][az];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const double C = dE[0][ax] + drho * E[0][ax];
+                const double geq = A * C + w1(ax - 1) * B;
+                fneq[3 * yz + ax] = (R)((double)f[3 * yz + ax] - geq);
+            }
+        }
+        // --- 3-4 in FP32: the moment differences are moments of f - f^eq ----
+        R M[3][3][3];
+        moments27<R>(fneq, M);
+        DMom<R> d;
+        d.T = M[2][0][0] + M[0][2][0] + M[0][0][2];
+        d.Nxz = M[2][0][0] - M[0][0][2];
+        d.Nyz = M[0][2][0] - M[0][0][2];
+        d.Pxy = M[1][1][0];
+        d.Pxz = M[1][0][1];
+        d.Pyz = M[0][1][1];
+        d.Qxyy = M[1][2][0];
+        d.Qxzz = M[1][0][2];
+        d.Qxxy = M[2][1][0];
+        d.Qyzz = M[0][1][2];
+        d.Qxxz = M[2][0][1];
+        d.Qyyz = M[0][2][1];
+        d.Qxyz = M[1][1][1];
+        R iE[3][3], Ef[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Ef[a][k] = (R)E[a][k];
+            recip3<R>(Ef[a], iE[a]);
+        }
+        R iA9[9], iCx[3];
+#pragma unroll
+        for (int yz = 0; yz < 9; ++yz) iA9[yz] = iE[1][yz % 3] * iE[2][yz / 3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) iCx[ax] = (R)irho * iE[0][ax];
+        kbc_relax<R, V>(f, d, [&](int i) -> R { return fneq[i]; }, iCx, iA9, rho, c);
+    } else {
+        // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ----
+        R M[3][3][3];
+        moments27<R>(f, M);
+        // rho and u (deviation forms: rho = 1 + sum g, sum v W = 0)
+        const R drho = DEV ? M[0][0][0] : M[0][0][0] - R(1);
+        const R rho = DEV ? R(1) + drho : M[0][0][0];
+        const R irho = R(1) / rho;
+        const R u[3] = {M[1][0][0] * irho, M[0][1][0] * irho, M[0][0][1] * irho};
+
+        // --- 2. one-dimensional equilibrium marginals ----------------------
+        R E[3][3], dE[3][3], dm2[3], m2[3], iE[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            marginals1d<R, DEV>(u[a], E[a], dE[a], dm2[a]);
+            m2[a] = R(1.0 / 3.0) + dm2[a];
+            recip3<R>(E[a], iE[a]);
+        }
+
+        // --- 3-4. moment differences; equilibrium moments in closed form ---
+        // rho m_p(u_x) m_q(u_y) m_r(u_z); the second-order diagonal ones
+        // carry the weights' share 1/3 in the deviation forms
+        R dD[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R Mdiag = a == 0 ? M[2][0][0] : (a == 1 ? M[0][2][0] : M[0][0][2]);
+            if constexpr (DEV) dD[a] = Mdiag - (drho * R(1.0 / 3.0) + rho * dm2[a]);
+            else dD[a] = Mdiag - rho * m2[a];
+        }
+        DMom<R> d;
+        d.T = dD[0] + dD[1] + dD[2];
+        d.Nxz = dD[0] - dD[2];
+        d.Nyz = dD[1] - dD[2];
+        d.Pxy = M[1][1][0] - rho * u[0] * u[1];
+        d.Pxz = M[1][0][1] - rho * u[0] * u[2];
+        d.Pyz = M[0][1][1] - rho * u[1] * u[2];
+        d.Qxyy = M[1][2][0] - rho * u[0] * m2[1];
+        d.Qxzz = M[1][0][2] - rho * u[0] * m2[2];
+        d.Qxxy = M[2][1][0] - rho * m2[0] * u[1];
+        d.Qyzz = M[0][1][2] - rho * u[1] * m2[2];
+        d.Qxxz = M[2][0][1] - rho * m2[0] * u[2];
+        d.Qyyz = M[0][2][1] - rho * m2[1] * u[2];
+        d.Qxyz = M[1][1][1] - rho * u[0] * u[1] * u[2];
+
+        // equilibrium (or its deviation from W) and 1/f^eq, from the marginals
+        R A9[9], B9[9], iA9[9];
+#pragma unroll
+        for (int yz = 0; yz < 9; ++yz) {
+            const int ay = yz % 3, az = yz / 3;
+            A9[yz] = E[1][ay] * E[2][az];
+            iA9[yz] = iE[1][ay] * iE[2][az];
+            if constexpr (DEV) B9[yz] = dE[1][ay] * E[2][az] + R(w1(ay - 1)) * dE[2][az];
+            else B9[yz] = R(0);
+        }
+        R Cx[3], iCx[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if constexpr (DEV) Cx[ax] = dE[0][ax] + drho * E[0][ax];
+            else Cx[ax] = rho * E[0][ax];
+            iCx[ax] = irho * iE[0][ax];
+        }
+        // f_i - f_i^eq, re-formed in each pass to keep register pressure low
+        auto fneq_of = [&](int i) -> R {
+            const int ax = i % 3, yz = i / 3;
+            if constexpr (DEV) return f[i] - (A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
+            else return f[i] - A9[yz] * Cx[ax];
+        };
+        kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, (double)rho, c);
     }
 }
 

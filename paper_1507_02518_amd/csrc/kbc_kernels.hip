@@ -460,6 +460,7 @@ hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
     switch (storage) {
     case ST_F64: fn = step_fn_v<ST_F64>(variant, sweep); break;
     case ST_F32: fn = step_fn_v<ST_F32>(variant, sweep); break;
+    case ST_F32X: fn = step_fn_v<ST_F32X>(variant, sweep); break;
     default: fn = step_fn_v<ST_F16>(variant, sweep); break;
     }
     hipLaunchKernelGGL(fn, dim3(grid_for(p.g.nnodes)), dim3(kBlock), 0, stream, p);
@@ -469,6 +470,7 @@ hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
 hipError_t launch_init_feq(int storage, int layout, void* buf, const Geom& g, const float* scale,
                            const double* u, const double* rho, hipStream_t stream)
 {
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
     StoreCtx sc;
     for (int i = 0; i < 27; ++i) sc.scale[i] = scale ? scale[i] : 1.0f;
     const dim3 grid(grid_for(g.nnodes)), block(kBlock);
@@ -503,6 +505,7 @@ hipError_t launch_pop_dev_max(const Geom& g, const double* f, unsigned* max_bits
 hipError_t launch_gather_pop(int storage, int layout, const void* buf, const Geom& g,
                              const float* inv_scale, double* f, hipStream_t stream)
 {
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
     LoadCtx lc;
     for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
     const dim3 grid(grid_for(g.nnodes)), block(kBlock);
@@ -516,6 +519,7 @@ hipError_t launch_sample_pop(int storage, int layout, const void* buf, const Geo
                              const float* inv_scale, const uint32_t* nodes, int count,
                              double* out, hipStream_t stream)
 {
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
     LoadCtx lc;
     for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
     const dim3 grid((count + kBlock - 1) / kBlock), block(kBlock);
@@ -528,6 +532,7 @@ hipError_t launch_sample_pop(int storage, int layout, const void* buf, const Geo
 hipError_t launch_scatter_pop(int storage, int layout, void* buf, const Geom& g, const float* scale,
                               const double* f, hipStream_t stream)
 {
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
     StoreCtx sc;
     for (int i = 0; i < 27; ++i) sc.scale[i] = scale ? scale[i] : 1.0f;
     const dim3 grid(grid_for(g.nnodes)), block(kBlock);
@@ -541,6 +546,7 @@ hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& 
                           const float* inv_scale, double* rho, double* u, int* flag,
                           hipStream_t stream)
 {
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
     LoadCtx lc;
     for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
     const dim3 grid(grid_for(g.nnodes)), block(kBlock);

@@ -25,12 +25,11 @@ KBC_EUNSTABLE = -4
 KBC_ECAPACITY = -5
 KBC_ESTATE = -6
 
-F64, F32_DEV, F16_DEV = 0, 1, 2
+F64, F32_DEV, F16_DEV, F32_DEV_X = 0, 1, 2, 3
 S_D, S_DT, S_DQ, S_DTQ = 0, 1, 2, 3
 PULL, AA = 0, 1
 
-DTYPES = {"f64": F64, "f32": F32_DEV, "f16": F16_DEV}
-_ELEM = {F64: 8, F32_DEV: 4, F16_DEV: 2}
+DTYPES = {"f64": F64, "f32": F32_DEV, "f16": F16_DEV, "f32x": F32_DEV_X}
 
 
 class KbcError(RuntimeError):
