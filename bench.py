@@ -115,6 +115,50 @@ def copy_ceiling(kbc, torch, stream):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def ensemble_and_serving(kbc, args):
+    """Batched ensemble (64 boxes, 500 steps) and a served request trace,
+    each against a plain one-box-at-a-time loop on the same inputs."""
+    import tempfile
+
+    from paper_1507_02518_amd import serve
+
+    out = {}
+    cache = os.path.join(tempfile.gettempdir(), "kbc_pool_tune.txt")
+    if args.ensemble:
+        log("[bench] ensemble: 64 boxes, edges {24..96}, 500 steps, FP32 storage")
+        boxes = serve.ensemble_boxes(64, seed=0)
+        serve.run_ensemble(boxes[:16], kbc.F32_DEV_X, batched=True, tune_cache=cache)  # warm-up + tuning
+        pool = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=True, tune_cache=cache)
+        loop = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=False)
+        same = all(pool["results"][i] == loop["results"][i] for i in pool["results"])
+        out["ensemble"] = {
+            "boxes": len(boxes), "steps": 500, "storage": "f32dev_x",
+            "lattice_updates": pool["lattice_updates"],
+            "pool": {"wall_s": round(pool["wall_s"], 4), "mlups": round(pool["mlups"], 1),
+                     "launch": {"block": pool["launch"]["block"], "grid": pool["launch"]["grid"]}},
+            "loop": {"wall_s": round(loop["wall_s"], 4), "mlups": round(loop["mlups"], 1)},
+            "speedup": round(loop["wall_s"] / pool["wall_s"], 3),
+            "results_equal": same}
+        log(f"[bench]   pool {pool['mlups']:.0f} MLUPS vs loop {loop['mlups']:.0f} MLUPS, equal={same}")
+    if args.serve_requests > 0:
+        log(f"[bench] serving: {args.serve_requests} requests, Poisson 20/s")
+        trace = serve.serving_trace(args.serve_requests, rate=20.0, seed=0)
+        srv = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25, tune_cache=cache)
+        seq = serve.run_sequential(trace, kbc.F32_DEV_X)
+        same = all(srv["results"][i] == seq["results"][i] for i in srv["results"])
+        out["serving"] = {
+            "requests": len(trace), "rate_per_s": 20.0, "storage": "f32dev_x",
+            "hbm_budget_GB": 200, "lattice_updates": srv["lattice_updates"],
+            "pool": {"p50_s": round(srv["p50_s"], 3), "p99_s": round(srv["p99_s"], 3),
+                     "mlups": round(srv["mlups"], 1), "wall_s": round(srv["wall_s"], 3)},
+            "loop": {"p50_s": round(seq["p50_s"], 3), "p99_s": round(seq["p99_s"], 3),
+                     "mlups": round(seq["mlups"], 1), "wall_s": round(seq["wall_s"], 3)},
+            "results_equal": same}
+        log(f"[bench]   pool p50 {srv['p50_s']:.2f}s p99 {srv['p99_s']:.2f}s {srv['mlups']:.0f} MLUPS; "
+            f"loop p50 {seq['p50_s']:.2f}s p99 {seq['p99_s']:.2f}s {seq['mlups']:.0f} MLUPS")
+    return out
+
+
 def cpu_baseline(u, steps):
     import oracle
 
@@ -137,6 +181,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-ensemble", dest="ensemble", action="store_false")
+    ap.add_argument("--serve-requests", type=int, default=96)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the KBC box runs on a single MI355X "
@@ -179,6 +225,8 @@ def main():
     del u_dev
     torch.cuda.empty_cache()
 
+    batched = ensemble_and_serving(kbc, args)
+
     traffic_bytes = read_counters()
     roofline = {
         "bound": "hbm",
@@ -219,6 +267,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    out.update(batched)
     print(json.dumps(out), flush=True)
 
 

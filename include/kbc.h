@@ -156,6 +156,72 @@ int kbc_bytes_per_node_step(kbc_handle h, double* bytes);
 /* The stream the box enqueues on (a hipStream_t). */
 int kbc_stream(kbc_handle h, void** stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble ("pool"): continuous batching of many independent boxes.
+ *
+ * A pool owns an HBM arena of hbm_budget_bytes.  Each admitted box (any
+ * shape, its own viscosity and step count) takes 27 * N * bytes-per-
+ * population of it and is updated in place with the AA pattern.  One
+ * kbc_pool_advance(g) enqueues up to g steps for every unfinished box at once
+ * (two launches per step, one per AA parity group, replayed from a captured
+ * hipGraph), so boxes admitted while others run share the GPU from their
+ * first step on.  Each box evolves exactly as the same box alone (same
+ * kernels, same arithmetic), so results do not depend on the mix.  Launch
+ * shape (tile = block size, persistent grid size) comes from an online
+ * autotuner that times its candidates on the first batches of real work and
+ * keeps the fastest per dtype and variant in tune_cache (may be NULL).
+ * ------------------------------------------------------------------------ */
+typedef struct kbc_pool* kbc_pool_handle;
+
+/* Create a pool.  dtype and opt (variant, gamma options, device, stream) as
+ * for kbc_create; opt->streaming is ignored.  max_slots in [1, 65536] bounds
+ * the number of resident boxes.  KBC_ENOMEM if the arena cannot be had. */
+int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* opt,
+                    int32_t max_slots, const char* tune_cache, kbc_pool_handle* out);
+
+/* Wait for all work and release every resource.  NULL is accepted. */
+int kbc_pool_destroy(kbc_pool_handle p);
+
+/* Admit a box of shape {nx, ny, nz}, viscosity nu, initial velocity u (host
+ * [3][nz][ny][nx] FP64, rho = 1) that will run `steps` steps.  Returns its
+ * slot in *slot.  KBC_ECAPACITY (nothing changed) if no slot is free or the
+ * arena has no contiguous room; KBC_EUNSTABLE if some |u_a| >= 1.
+ * Synchronises only with the pool's own admission stream, not with running
+ * batches. */
+int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const double* u,
+                   int64_t steps, int32_t* slot);
+
+/* Enqueue a batch: every resident box with steps left runs min(g, left)
+ * steps, g in [1, 4096].  Returns without waiting. */
+int kbc_pool_advance(kbc_pool_handle p, int64_t g);
+
+/* Steps of the box not yet completed on the device (0 = result ready).
+ * Does not block. */
+int kbc_pool_poll(kbc_pool_handle p, int32_t slot, int64_t* remaining);
+
+/* For a box that has run all its steps: kinetic energy k and enstrophy Omega
+ * (as kbc_energy / kbc_enstrophy) and optionally rho [nz][ny][nx] and
+ * u [3][nz][ny][nx] (host, may be NULL).  Waits for the box's last batch
+ * only.  KBC_ESTATE if steps are left; KBC_EUNSTABLE if the state is not
+ * finite (other boxes are unaffected). */
+int kbc_pool_result(kbc_pool_handle p, int32_t slot, double* k, double* omega, double* rho,
+                    double* u);
+
+/* Free the box's slot and arena region (waits for its last batch). */
+int kbc_pool_release(kbc_pool_handle p, int32_t slot);
+
+/* Wait for every enqueued batch. */
+int kbc_pool_sync(kbc_pool_handle p);
+
+/* Arena bytes in use, resident boxes, current launch shape and whether the
+ * tuner is still measuring (any pointer may be NULL). */
+int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t* block,
+                  int32_t* grid, int32_t* tuning);
+
+/* Fix the launch shape (block: 64..512 in steps of 64; grid >= 1) and stop
+ * tuning. */
+int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid);
+
 /* Measurement utility (not part of the method): copy `bytes` (a multiple of
  * 16) from device src to device dst with a plain streaming kernel on the
  * given hipStream_t (NULL = default stream), without synchronising.  Its

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkbc.so")
-SOURCES = ["kbc_kernels.hip", "kbc_api.hip"]
+SOURCES = ["kbc_kernels.hip", "kbc_api.hip", "kbc_pool.hip"]
 ARCH = os.environ.get("KBC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -44,7 +44,19 @@ size_t elem_bytes(int dtype)
     return dtype == KBC_F64 ? 8 : (dtype == KBC_F16_DEV ? 2 : 4);
 }
 
+#ifndef KBC_PLANE_PAD_BYTES
+#define KBC_PLANE_PAD_BYTES 0
+#endif
+
+uint64_t plane_pad_elems(uint64_t nnodes, size_t elem)
+{
+    if (KBC_PLANE_PAD_BYTES == 0 || nnodes < 65536) return 0;
+    return (uint64_t)KBC_PLANE_PAD_BYTES / elem;
+}
+
 }  // namespace
+
+void kbc::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
 struct kbc_box {
     int64_t shape[3];
@@ -192,7 +204,9 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     h->g.nnodes = (uint32_t)(shape[0] * shape[1] * shape[2]);
     h->g.dnx = make_fastdiv(h->g.nx);
     h->g.dny = make_fastdiv(h->g.ny);
-    h->g.plane = h->g.nnodes;
+    // distance between direction planes: the node count plus a pad that keeps
+    // the 27 read and 27 write streams off a common power-of-two stride
+    h->g.plane = h->g.nnodes + plane_pad_elems(h->g.nnodes, elem_bytes(dtype));
     h->dtype = dtype;
     h->variant = opt.variant;
     h->streaming = opt.streaming;
@@ -232,7 +246,7 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
         }
         h->own_stream = true;
     }
-    const size_t bytes = 27ull * h->g.nnodes * elem_bytes(dtype);
+    const size_t bytes = 27ull * h->g.plane * elem_bytes(dtype);
     const int nbuf = h->streaming == KBC_PULL ? 2 : 1;
     for (int b = 0; b < nbuf; ++b) {
         e = hipMalloc(&h->buf[b], bytes);

@@ -15,6 +15,9 @@ namespace kbc {
 //   AA:    even t: F_i(x, t) = buf[i][x]; odd t: F_i(x, t) = buf[26-i][x - v_i].
 enum Layout : int { LY_PULL = 0, LY_AA_EVEN = 1, LY_AA_ODD = 2 };
 
+// Record the message returned by kbc_last_error() on this thread.
+void set_last_error(const char* msg);
+
 // One time step of one box (src -> dst for pull; in place for AA).
 hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
                        hipStream_t stream);
@@ -66,5 +69,34 @@ hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t str
 int reduce_partials();
 hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double* mean_sum,
                          double* partial, double* out, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Batched ensemble (pool): many independent AA boxes advanced by one launch.
+// ---------------------------------------------------------------------------
+struct PoolBox {
+    void* buf;            // the box's population array (AA layout, in place)
+    Geom g;
+    Coll c;
+    uint32_t tile0;       // first tile of the box in the current batch
+    uint32_t ntiles;      // ceil(nnodes / tile_nodes)
+    int32_t parity0;      // t mod 2 at the start of the batch
+    int32_t steps;        // steps the box takes in the current batch
+    float scale[27], inv_scale[27];
+};
+
+struct PoolMeta {
+    uint32_t n_active;    // boxes in the table, sorted by tile0
+    uint32_t n_tiles;     // total tiles
+    uint32_t tile_nodes;  // nodes per tile (= threads per block)
+    uint32_t pad_;
+};
+
+constexpr int kPoolMaxBlock = 512;
+
+// Step k (0-based) of a batch for one parity group: every box of the table
+// with k < steps applies the AA sweep `sweep` (SW_AA_EVEN or SW_AA_ODD).
+// Persistent grid-stride loop over the group's tiles; block <= 512.
+hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
+                            const PoolMeta* meta, int k, int block, int grid, hipStream_t stream);
 
 }  // namespace kbc

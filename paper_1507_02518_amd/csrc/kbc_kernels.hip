@@ -16,6 +16,25 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Build-time tuning of the step kernel (chosen by measurement).
+#ifndef KBC_STEP_BLOCK
+#define KBC_STEP_BLOCK 256
+#endif
+#ifndef KBC_NT_STORE
+#define KBC_NT_STORE 1
+#endif
+#ifndef KBC_WAVES_PER_EU
+#define KBC_WAVES_PER_EU 0
+#endif
+constexpr int kStepBlock = KBC_STEP_BLOCK;
+
+template <typename T>
+__device__ __forceinline__ void st_pop(T* p, T v)
+{
+    if constexpr (KBC_NT_STORE && sizeof(T) >= 4) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 __device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t n)
 {
     // a in [0, n), d in {-1, 0, 1}
@@ -29,66 +48,158 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
     return (z * g.ny + y) * g.nx + x;
 }
 
-// ---------------------------------------------------------------------------
-// Fused step: one thread per node; 27 gathered loads, collision, 27 stores.
+// One node of one step: 27 gathered loads, the collision, 27 stores.
 //   pull:    read src[i][x - v_i], write dst[i][x]
 //   AA even: read buf[i][x],        write buf[26-i][x]
 //   AA odd:  read buf[26-i][x - v_i], write buf[i][x + v_i]
 // In both AA sweeps a node reads and writes the same 27 locations, so the
 // in-place update is free of races between nodes.
-// ---------------------------------------------------------------------------
 template <int S, int V, int SW>
-__global__ void __launch_bounds__(kBlock) k_step(StepParams p)
+__device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
+                                            const Coll& c, const float* scale,
+                                            const float* inv_scale, uint32_t n)
 {
     using T = typename Traits<S>::T;
     using R = typename Traits<S>::R;
-    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= p.g.nnodes) return;
-
     uint32_t x, y, z;
-    node_xyz(n, p.g, x, y, z);
-    const uint32_t xm = x == 0 ? p.g.nx - 1 : x - 1, xp = x + 1 == p.g.nx ? 0 : x + 1;
-    const uint32_t ym = y == 0 ? p.g.ny - 1 : y - 1, yp = y + 1 == p.g.ny ? 0 : y + 1;
-    const uint32_t zm = z == 0 ? p.g.nz - 1 : z - 1, zp = z + 1 == p.g.nz ? 0 : z + 1;
+    node_xyz(n, g, x, y, z);
+    const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+    const uint32_t ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
+    const uint32_t zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
     // coordinate of x - v along each axis, indexed by v + 1
     const uint32_t bx[3] = {xp, x, xm};
-    const uint32_t byo[3] = {yp * p.g.nx, y * p.g.nx, ym * p.g.nx};
-    const uint32_t bzo[3] = {zp * p.g.ny * p.g.nx, z * p.g.ny * p.g.nx, zm * p.g.ny * p.g.nx};
-    // coordinate of x + v
-    const uint32_t fx[3] = {xm, x, xp};
-    const uint32_t fyo[3] = {ym * p.g.nx, y * p.g.nx, yp * p.g.nx};
-    const uint32_t fzo[3] = {zm * p.g.ny * p.g.nx, z * p.g.ny * p.g.nx, zp * p.g.ny * p.g.nx};
+    const uint32_t byo[3] = {yp * g.nx, y * g.nx, ym * g.nx};
+    const uint32_t bzo[3] = {zp * g.ny * g.nx, z * g.ny * g.nx, zm * g.ny * g.nx};
 
-    const T* __restrict__ src = static_cast<const T*>(p.src);
-    T* __restrict__ dst = static_cast<T*>(p.dst);
-    const uint64_t plane = p.g.plane;
+    const T* __restrict__ src = static_cast<const T*>(srcv);
+    T* __restrict__ dst = static_cast<T*>(dstv);
+    const uint64_t plane = g.plane;
 
     R f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            f[i] = decode<S>(src[i * plane + (bzo[az] + byo[ay] + bx[ax])], p.inv_scale[i]);
+            f[i] = decode<S>(src[i * plane + (bzo[az] + byo[ay] + bx[ax])], inv_scale[i]);
         } else if constexpr (SW == SW_AA_EVEN) {
-            f[i] = decode<S>(src[i * plane + n], p.inv_scale[i]);
+            f[i] = decode<S>(src[i * plane + n], inv_scale[i]);
         } else {
             f[i] = decode<S>(src[opp(i) * plane + (bzo[az] + byo[ay] + bx[ax])],
-                             p.inv_scale[opp(i)]);
+                             inv_scale[opp(i)]);
         }
     }
 
-    collide<S, V>(f, p.c);
+    if constexpr (SW != SW_PULL) {
+        // AA sweeps read and write the same 27 locations through src and
+        // dst (one buffer): every load is issued before any store, and the
+        // compiler may not move memory accesses across this point
+        asm volatile("" ::: "memory");
+    }
+
+    collide<S, V>(f, c);
+
+    // AA odd sweep: store offsets x + v are formed after the collision, from
+    // the coordinates alone, so they do not occupy registers across it (the
+    // empty asm only hides the coordinates from common-subexpression reuse)
+    uint32_t fx[3] = {0, 0, 0}, fyo[3] = {0, 0, 0}, fzo[3] = {0, 0, 0};
+    if constexpr (SW == SW_AA_ODD) {
+        uint32_t x2 = x, y2 = y, z2 = z;
+        asm volatile("" : "+v"(x2), "+v"(y2), "+v"(z2));
+        const uint32_t plane_xy = g.ny * g.nx;
+        fx[0] = x2 == 0 ? g.nx - 1 : x2 - 1;
+        fx[1] = x2;
+        fx[2] = x2 + 1 == g.nx ? 0 : x2 + 1;
+        fyo[0] = (y2 == 0 ? g.ny - 1 : y2 - 1) * g.nx;
+        fyo[1] = y2 * g.nx;
+        fyo[2] = (y2 + 1 == g.ny ? 0 : y2 + 1) * g.nx;
+        fzo[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * plane_xy;
+        fzo[1] = z2 * plane_xy;
+        fzo[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * plane_xy;
+    }
 
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            dst[i * plane + n] = encode<S>(f[i], p.scale[i]);
+            st_pop(&dst[i * plane + n], encode<S>(f[i], scale[i]));
         } else if constexpr (SW == SW_AA_EVEN) {
-            dst[opp(i) * plane + n] = encode<S>(f[i], p.scale[opp(i)]);
+            st_pop(&dst[opp(i) * plane + n], encode<S>(f[i], scale[opp(i)]));
         } else {
-            dst[i * plane + (fzo[az] + fyo[ay] + fx[ax])] = encode<S>(f[i], p.scale[i]);
+            st_pop(&dst[i * plane + (fzo[az] + fyo[ay] + fx[ax])], encode<S>(f[i], scale[i]));
         }
+    }
+}
+
+// Fused step of one box: one thread per node.
+template <int S, int V, int SW>
+__global__ void __launch_bounds__(kStepBlock)
+#if KBC_WAVES_PER_EU
+__attribute__((amdgpu_waves_per_eu(KBC_WAVES_PER_EU, 8)))
+#endif
+k_step(StepParams p)
+{
+    const uint32_t n = blockIdx.x * kStepBlock + threadIdx.x;
+    if (n >= p.g.nnodes) return;
+    node_update<S, V, SW>(p.src, p.dst, p.g, p.c, p.scale, p.inv_scale, n);
+}
+
+// Batched step over one parity group of a pool's boxes (AA sweep SW, in
+// place).  Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; a
+// tile belongs to the last box whose first tile is not after it (binary
+// search over the table, sorted by first tile).  Boxes are disjoint in
+// memory and each node is updated by exactly one thread, so a box evolves
+// exactly as it would alone.
+template <int S, int V, int SW>
+__global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ boxes,
+                                                             const PoolMeta* __restrict__ meta,
+                                                             int k)
+{
+    const uint32_t n_tiles = meta->n_tiles;
+    const uint32_t n_active = meta->n_active;
+    const uint32_t tn = meta->tile_nodes;
+#pragma unroll 1
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint32_t lo = 0, hi = n_active;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (boxes[mid].tile0 <= tile) lo = mid;
+            else hi = mid;
+        }
+        const PoolBox& b = boxes[lo];
+        // the box's constants as values, so the population stores cannot be
+        // taken to alias them
+        const Geom g = b.g;
+        const Coll c = b.c;
+        void* const buf = b.buf;
+        const int steps = b.steps;
+        const uint32_t n = (tile - b.tile0) * tn + threadIdx.x;
+        if (k < steps && n < g.nnodes) {
+            // the store side sees the buffer through a second pointer, as in
+            // the single-box kernel (loads and stores are kept apart by the
+            // barrier in node_update)
+            void* dbuf = buf;
+            asm volatile("" : "+s"(dbuf));
+            node_update<S, V, SW>(buf, dbuf, g, c, b.scale, b.inv_scale, n);
+        }
+    }
+}
+
+using PoolFn = void (*)(const PoolBox*, const PoolMeta*, int);
+
+template <int S, int V>
+PoolFn pool_fn_sw(int sw)
+{
+    return sw == SW_AA_EVEN ? k_pool_step<S, V, SW_AA_EVEN> : k_pool_step<S, V, SW_AA_ODD>;
+}
+
+template <int S>
+PoolFn pool_fn_v(int v, int sw)
+{
+    switch (v) {
+    case V_D: return pool_fn_sw<S, V_D>(sw);
+    case V_DT: return pool_fn_sw<S, V_DT>(sw);
+    case V_DQ: return pool_fn_sw<S, V_DQ>(sw);
+    default: return pool_fn_sw<S, V_DTQ>(sw);
     }
 }
 
@@ -463,7 +574,24 @@ hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
     case ST_F32X: fn = step_fn_v<ST_F32X>(variant, sweep); break;
     default: fn = step_fn_v<ST_F16>(variant, sweep); break;
     }
-    hipLaunchKernelGGL(fn, dim3(grid_for(p.g.nnodes)), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL(fn, dim3((p.g.nnodes + kStepBlock - 1) / kStepBlock), dim3(kStepBlock), 0,
+                       stream, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
+                            const PoolMeta* meta, int k, int block, int grid, hipStream_t stream)
+{
+    if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 1) return hipErrorInvalidValue;
+    if (sweep != SW_AA_EVEN && sweep != SW_AA_ODD) return hipErrorInvalidValue;
+    PoolFn fn;
+    switch (storage) {
+    case ST_F64: fn = pool_fn_v<ST_F64>(variant, sweep); break;
+    case ST_F32: fn = pool_fn_v<ST_F32>(variant, sweep); break;
+    case ST_F32X: fn = pool_fn_v<ST_F32X>(variant, sweep); break;
+    default: fn = pool_fn_v<ST_F16>(variant, sweep); break;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, boxes, meta, k);
     return hipGetLastError();
 }
 

@@ -1,0 +1,693 @@
+// kbc_pool.hip -- batched ensemble ("pool") of independent periodic boxes
+// for continuous batching (declared in include/kbc.h).
+//
+// A pool owns one HBM arena sized by the caller's budget.  Each admitted box
+// gets a contiguous region of the arena holding its populations in the AA
+// in-place layout (one lattice).  A batch of g steps advances every
+// unfinished box by up to g steps: per step two launches of the pool kernel,
+// one per AA parity group, each a persistent grid-stride loop over the tiles
+// of all boxes of that group.  The g steps are captured once in a hipGraph
+// and replayed; the box table the kernels read lives at fixed device
+// addresses and is uploaded before each batch, so admissions and releases
+// never invalidate a graph.  Boxes differ in size, viscosity and step count.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <new>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kbc.h"
+#include "kbc_internal.h"
+
+using namespace kbc;
+
+namespace {
+
+int pfail(int code, const std::string& msg)
+{
+    set_last_error(msg.c_str());
+    return code;
+}
+
+int phip(hipError_t e, const char* where)
+{
+    if (e == hipErrorOutOfMemory) return pfail(KBC_ENOMEM, std::string(where) + ": out of device memory");
+    return pfail(KBC_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define PHIP(call)                                          \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return phip(e_, #call);       \
+    } while (0)
+
+size_t elem_bytes_of(int dtype) { return dtype == KBC_F64 ? 8 : (dtype == KBC_F16_DEV ? 2 : 4); }
+
+// First-fit allocator over [0, size) in units of kGrain bytes; free blocks
+// are kept by offset and coalesced on release.
+class Arena {
+public:
+    static constexpr size_t kGrain = 65536;
+    void reset(size_t size)
+    {
+        free_.clear();
+        size_ = size / kGrain * kGrain;
+        if (size_) free_[0] = size_;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        const size_t need = (bytes + kGrain - 1) / kGrain * kGrain;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= need) {
+                *off = it->first;
+                const size_t rest = it->second - need;
+                const size_t start = it->first + need;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += need;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        const size_t need = (bytes + kGrain - 1) / kGrain * kGrain;
+        used_ -= need;
+        auto it = free_.emplace(off, need).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+struct Event {
+    hipEvent_t e = nullptr;
+    ~Event()
+    {
+        if (e) (void)hipEventDestroy(e);
+    }
+    bool done() const { return hipEventQuery(e) == hipSuccess; }
+};
+
+struct Slot {
+    bool used = false;
+    Geom g{};
+    Coll c{};
+    size_t off = 0, bytes = 0;
+    int64_t t = 0;          // steps enqueued
+    int64_t t_prev = 0;     // steps enqueued before the last batch
+    int64_t target = 0;     // steps requested
+    std::shared_ptr<Event> last;
+    float scale[27], inv_scale[27];
+};
+
+struct LaunchCfg {
+    int block, grid;
+};
+
+}  // namespace
+
+struct kbc_pool {
+    int dtype = 0, variant = KBC_S_DTQ, device = 0;
+    Coll defaults{};
+    hipStream_t stream = nullptr, admit_stream = nullptr, diag_stream = nullptr;
+    bool own_stream = false;
+    char* arena_base = nullptr;
+    Arena arena;
+    std::vector<Slot> slots;
+    PoolBox* d_boxes[2] = {nullptr, nullptr};
+    PoolMeta* d_meta[2] = {nullptr, nullptr};
+    PoolBox* h_boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    PoolMeta* h_meta[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipEvent_t mirror_ev[2] = {nullptr, nullptr};
+    bool mirror_used[2] = {false, false};
+    int mirror = 0;
+    std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;
+    std::vector<std::tuple<int64_t, int, int>> graph_order;
+    LaunchCfg cfg{256, 1024};
+    bool tuning = false;
+    std::vector<LaunchCfg> cands;
+    std::vector<double> cand_cost;
+    size_t cand_next = 0;
+    hipEvent_t tev0 = nullptr, tev1 = nullptr;
+    bool timing_pending = false;
+    int timing_cand = -1;
+    double timing_node_steps = 0;
+    std::string tune_cache;
+    int cus = 256;
+    // staging and diagnostics scratch (grown on demand)
+    double* d_stage = nullptr;
+    size_t stage_cap = 0;
+    double* d_u = nullptr;
+    size_t u_cap = 0;
+    double* d_rho = nullptr;
+    double* d_partial = nullptr;
+    double* d_sum = nullptr;
+    int* d_flag = nullptr;
+    unsigned* d_max = nullptr;
+};
+
+namespace {
+
+int ensure_stage(kbc_pool* p, size_t nnodes)
+{
+    if (p->stage_cap < nnodes) {
+        if (p->d_stage) PHIP(hipFree(p->d_stage));
+        p->d_stage = nullptr;
+        PHIP(hipMalloc(&p->d_stage, 3 * nnodes * sizeof(double)));
+        p->stage_cap = nnodes;
+    }
+    return KBC_OK;
+}
+
+int ensure_diag(kbc_pool* p, size_t nnodes)
+{
+    if (p->u_cap < nnodes) {
+        if (p->d_u) PHIP(hipFree(p->d_u));
+        if (p->d_rho) PHIP(hipFree(p->d_rho));
+        p->d_u = nullptr;
+        p->d_rho = nullptr;
+        PHIP(hipMalloc(&p->d_u, 3 * nnodes * sizeof(double)));
+        PHIP(hipMalloc(&p->d_rho, nnodes * sizeof(double)));
+        p->u_cap = nnodes;
+    }
+    return KBC_OK;
+}
+
+std::string cache_key(const kbc_pool* p)
+{
+    std::ostringstream os;
+    os << "gfx950 dtype=" << p->dtype << " variant=" << p->variant;
+    return os.str();
+}
+
+void load_tune_cache(kbc_pool* p)
+{
+    if (p->tune_cache.empty()) return;
+    std::ifstream in(p->tune_cache);
+    std::string line, key = cache_key(p);
+    while (std::getline(in, line)) {
+        const size_t bar = line.find('|');
+        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        std::istringstream rest(line.substr(bar + 1));
+        int block = 0, grid = 0;
+        if (rest >> block >> grid && block >= 64 && block <= kPoolMaxBlock && block % 64 == 0 && grid > 0) {
+            p->cfg = LaunchCfg{block, grid};
+            p->tuning = false;
+        }
+    }
+}
+
+void save_tune_cache(kbc_pool* p)
+{
+    if (p->tune_cache.empty()) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream in(p->tune_cache);
+        std::string line, key = cache_key(p);
+        while (std::getline(in, line))
+            if (line.substr(0, line.find('|')) != key && !line.empty()) keep.push_back(line);
+    }
+    std::ofstream out(p->tune_cache, std::ios::trunc);
+    for (auto& l : keep) out << l << "\n";
+    out << cache_key(p) << "|" << p->cfg.block << " " << p->cfg.grid << "\n";
+}
+
+// Collect a finished timing measurement of the online tuner, if any.
+void tuner_collect(kbc_pool* p, bool wait)
+{
+    if (!p->timing_pending) return;
+    if (!wait && hipEventQuery(p->tev1) != hipSuccess) return;
+    (void)hipEventSynchronize(p->tev1);
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p->tev0, p->tev1) == hipSuccess && p->timing_node_steps > 0) {
+        const double cost = ms / p->timing_node_steps;
+        double& slot = p->cand_cost[p->timing_cand];
+        slot = std::min(slot, cost);
+    }
+    p->timing_pending = false;
+    if (p->cand_next >= p->cands.size()) {
+        size_t best = 0;
+        for (size_t i = 1; i < p->cands.size(); ++i)
+            if (p->cand_cost[i] < p->cand_cost[best]) best = i;
+        p->cfg = p->cands[best];
+        p->tuning = false;
+        save_tune_cache(p);
+    }
+}
+
+void destroy_graphs(kbc_pool* p)
+{
+    for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    p->graph_order.clear();
+}
+
+int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, hipGraphExec_t* out)
+{
+    const auto key = std::make_tuple(steps, cfg.block, cfg.grid);
+    auto it = p->graphs.find(key);
+    if (it != p->graphs.end()) {
+        *out = it->second;
+        return KBC_OK;
+    }
+    if (p->graphs.size() >= 16) {
+        const auto old = p->graph_order.front();
+        p->graph_order.erase(p->graph_order.begin());
+        (void)hipGraphExecDestroy(p->graphs[old]);
+        p->graphs.erase(old);
+    }
+    hipGraph_t graph = nullptr;
+    PHIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int64_t k = 0; k < steps && err == hipSuccess; ++k) {
+        // group (k mod 2) is at even parity at step k, the other group odd
+        const int ge = (int)(k & 1), go = 1 - ge;
+        err = launch_pool_step(p->dtype, p->variant, SW_AA_EVEN, p->d_boxes[ge], p->d_meta[ge], (int)k,
+                               cfg.block, cfg.grid, p->stream);
+        if (err == hipSuccess)
+            err = launch_pool_step(p->dtype, p->variant, SW_AA_ODD, p->d_boxes[go], p->d_meta[go],
+                                   (int)k, cfg.block, cfg.grid, p->stream);
+    }
+    const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
+    if (err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return phip(err, "pool step capture");
+    }
+    if (e2 != hipSuccess) return phip(e2, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return phip(e3, "hipGraphInstantiate");
+    p->graphs[key] = exec;
+    p->graph_order.push_back(key);
+    *out = exec;
+    return KBC_OK;
+}
+
+int check_pool(kbc_pool_handle p)
+{
+    if (!p) return pfail(KBC_EINVAL, "null pool");
+    return KBC_OK;
+}
+
+int check_slot(kbc_pool_handle p, int32_t slot)
+{
+    if (int r = check_pool(p)) return r;
+    if (slot < 0 || slot >= (int32_t)p->slots.size() || !p->slots[slot].used)
+        return pfail(KBC_EINVAL, "no box in this slot");
+    return KBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* opt_in,
+                    int32_t max_slots, const char* tune_cache, kbc_pool_handle* out)
+{
+    if (!out) return pfail(KBC_EINVAL, "out is NULL");
+    *out = nullptr;
+    kbc_options opt;
+    if (opt_in) opt = *opt_in;
+    else kbc_options_default(&opt);
+    if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV && dtype != KBC_F32_DEV_X)
+        return pfail(KBC_EINVAL, "unknown dtype");
+    if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return pfail(KBC_EINVAL, "unknown variant");
+    if (max_slots < 1 || max_slots > 65536) return pfail(KBC_EINVAL, "max_slots must be in [1, 65536]");
+    if (hbm_budget_bytes < Arena::kGrain) return pfail(KBC_EINVAL, "budget below 64 KiB");
+    if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))
+        return pfail(KBC_EINVAL, "gamma_value must be finite");
+
+    std::unique_ptr<kbc_pool> p(new (std::nothrow) kbc_pool());
+    if (!p) return pfail(KBC_ENOMEM, "host allocation failed");
+    p->dtype = dtype;
+    p->variant = opt.variant;
+    p->defaults.gamma_fixed = opt.gamma_fixed ? 1 : 0;
+    p->defaults.gamma_value = opt.gamma_value;
+    p->defaults.gamma_eps = opt.gamma_eps > 0.0 ? opt.gamma_eps : (dtype == KBC_F64 ? 1e-28 : 1e-16);
+    int dev = opt.device;
+    if (dev < 0) PHIP(hipGetDevice(&dev));
+    p->device = dev;
+    PHIP(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        p->cus = prop.multiProcessorCount;
+    p->cfg = LaunchCfg{256, 4 * p->cus};
+    if (opt.stream) {
+        p->stream = (hipStream_t)opt.stream;
+    } else {
+        PHIP(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+        p->own_stream = true;
+    }
+    PHIP(hipStreamCreateWithFlags(&p->admit_stream, hipStreamNonBlocking));
+    PHIP(hipStreamCreateWithFlags(&p->diag_stream, hipStreamNonBlocking));
+    const hipError_t ea = hipMalloc(&p->arena_base, hbm_budget_bytes);
+    if (ea != hipSuccess) {
+        kbc_pool_destroy(p.release());
+        return phip(ea, "hipMalloc(arena)");
+    }
+    p->arena.reset(hbm_budget_bytes);
+    p->slots.resize((size_t)max_slots);
+    for (int grp = 0; grp < 2; ++grp) {
+        hipError_t e = hipMalloc(&p->d_boxes[grp], (size_t)max_slots * sizeof(PoolBox));
+        if (e == hipSuccess) e = hipMalloc(&p->d_meta[grp], sizeof(PoolMeta));
+        for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+            e = hipHostMalloc((void**)&p->h_boxes[m][grp], (size_t)max_slots * sizeof(PoolBox));
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_meta[m][grp], sizeof(PoolMeta));
+        }
+        if (e != hipSuccess) {
+            kbc_pool_destroy(p.release());
+            return phip(e, "pool tables");
+        }
+    }
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < 2 && e == hipSuccess; ++m)
+        e = hipEventCreateWithFlags(&p->mirror_ev[m], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&p->tev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->tev1);
+    if (e == hipSuccess) e = hipMalloc(&p->d_partial, 3 * (size_t)reduce_partials() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&p->d_sum, 8 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&p->d_flag, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_max, 27 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        kbc_pool_destroy(p.release());
+        return phip(e, "pool scratch");
+    }
+    // tuner candidates: tile (= block) sizes x persistent grid sizes
+    for (int block : {128, 256, 512})
+        for (int mult : {2, 4, 8, 16}) p->cands.push_back(LaunchCfg{block, mult * p->cus});
+    p->cand_cost.assign(p->cands.size(), 1e300);
+    p->tuning = true;
+    if (tune_cache) p->tune_cache = tune_cache;
+    load_tune_cache(p.get());
+    *out = p.release();
+    return KBC_OK;
+}
+
+int kbc_pool_destroy(kbc_pool_handle p)
+{
+    if (!p) return KBC_OK;
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->admit_stream) (void)hipStreamSynchronize(p->admit_stream);
+    if (p->diag_stream) (void)hipStreamSynchronize(p->diag_stream);
+    destroy_graphs(p);
+    for (auto& s : p->slots) s.last.reset();
+    for (int grp = 0; grp < 2; ++grp) {
+        if (p->d_boxes[grp]) (void)hipFree(p->d_boxes[grp]);
+        if (p->d_meta[grp]) (void)hipFree(p->d_meta[grp]);
+        for (int m = 0; m < 2; ++m) {
+            if (p->h_boxes[m][grp]) (void)hipHostFree(p->h_boxes[m][grp]);
+            if (p->h_meta[m][grp]) (void)hipHostFree(p->h_meta[m][grp]);
+        }
+    }
+    for (int m = 0; m < 2; ++m)
+        if (p->mirror_ev[m]) (void)hipEventDestroy(p->mirror_ev[m]);
+    if (p->tev0) (void)hipEventDestroy(p->tev0);
+    if (p->tev1) (void)hipEventDestroy(p->tev1);
+    for (void* q : {(void*)p->arena_base, (void*)p->d_stage, (void*)p->d_u, (void*)p->d_rho,
+                    (void*)p->d_partial, (void*)p->d_sum, (void*)p->d_flag, (void*)p->d_max})
+        if (q) (void)hipFree(q);
+    if (p->admit_stream) (void)hipStreamDestroy(p->admit_stream);
+    if (p->diag_stream) (void)hipStreamDestroy(p->diag_stream);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return KBC_OK;
+}
+
+int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const double* u,
+                   int64_t steps, int32_t* slot_out)
+{
+    if (int r = check_pool(p)) return r;
+    if (!shape || !u || !slot_out) return pfail(KBC_EINVAL, "shape, u or slot is NULL");
+    *slot_out = -1;
+    for (int a = 0; a < 3; ++a)
+        if (shape[a] < 1) return pfail(KBC_EINVAL, "shape entries must be >= 1");
+    const double nn = (double)shape[0] * (double)shape[1] * (double)shape[2];
+    if (nn >= 2147483648.0) return pfail(KBC_EINVAL, "box has 2^31 nodes or more");
+    if (!(nu > 0.0) || !std::isfinite(nu)) return pfail(KBC_EINVAL, "nu must be finite and > 0");
+    if (steps < 0) return pfail(KBC_EINVAL, "steps must be >= 0");
+    int32_t slot = -1;
+    for (size_t i = 0; i < p->slots.size(); ++i)
+        if (!p->slots[i].used) {
+            slot = (int32_t)i;
+            break;
+        }
+    if (slot < 0) return pfail(KBC_ECAPACITY, "all pool slots are in use");
+    const uint64_t nnodes = (uint64_t)(shape[0] * shape[1] * shape[2]);
+    const size_t bytes = 27ull * nnodes * elem_bytes_of(p->dtype);
+    size_t off = 0;
+    if (!p->arena.alloc(bytes, &off)) return pfail(KBC_ECAPACITY, "HBM budget exhausted");
+    PHIP(hipSetDevice(p->device));
+    Slot s;
+    s.g.nx = (uint32_t)shape[0];
+    s.g.ny = (uint32_t)shape[1];
+    s.g.nz = (uint32_t)shape[2];
+    s.g.nnodes = (uint32_t)nnodes;
+    s.g.dnx = make_fastdiv(s.g.nx);
+    s.g.dny = make_fastdiv(s.g.ny);
+    s.g.plane = nnodes;
+    s.c = p->defaults;
+    const double beta = 1.0 / (6.0 * nu + 1.0);  // nu = (1/3)(1/(2 beta) - 1/2)
+    s.c.beta = beta;
+    s.c.inv_beta = 1.0 / beta;
+    s.c.c2 = 2.0 - 1.0 / beta;
+    s.off = off;
+    s.bytes = bytes;
+    s.target = steps;
+    for (int i = 0; i < 27; ++i) s.scale[i] = s.inv_scale[i] = 1.0f;
+    auto undo = [&](int code) {
+        p->arena.release(off, bytes);
+        return code;
+    };
+    if (int r = ensure_stage(p, nnodes)) return undo(r);
+    void* buf = p->arena_base + off;
+    hipError_t e = hipMemcpyAsync(p->d_stage, u, 3 * nnodes * sizeof(double), hipMemcpyHostToDevice,
+                                  p->admit_stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_flag, 0, sizeof(int), p->admit_stream);
+    if (e == hipSuccess) e = launch_check_init(s.g, p->d_stage, nullptr, p->d_flag, p->admit_stream);
+    int flag = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, p->admit_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->admit_stream);
+    if (e != hipSuccess) return undo(phip(e, "kbc_pool_admit"));
+    if (flag) return undo(pfail(KBC_EUNSTABLE, "initial state has |u_a| >= 1 (equilibrium not positive)"));
+    if (p->dtype == KBC_F16_DEV) {
+        unsigned mb[27];
+        e = launch_feq_dev_max(s.g, p->d_stage, nullptr, p->d_max, p->admit_stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(mb, p->d_max, sizeof(mb), hipMemcpyDeviceToHost, p->admit_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->admit_stream);
+        if (e != hipSuccess) return undo(phip(e, "kbc_pool_admit scales"));
+        for (int i = 0; i < 27; ++i) {
+            float m0, m1;
+            std::memcpy(&m0, &mb[i], sizeof(float));
+            std::memcpy(&m1, &mb[26 - i], sizeof(float));
+            double m = std::max<double>(m0, m1);
+            m = std::max(m, 1e-4 * weight(i));
+            const int ex = (int)std::floor(std::log2(4096.0 / m));
+            s.scale[i] = std::ldexp(1.0f, ex);
+            s.inv_scale[i] = std::ldexp(1.0f, -ex);
+        }
+    }
+    e = launch_init_feq(p->dtype, LY_AA_EVEN, buf, s.g, s.scale, p->d_stage, nullptr, p->admit_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->admit_stream);
+    if (e != hipSuccess) return undo(phip(e, "kbc_pool_admit init"));
+    s.used = true;
+    p->slots[slot] = s;
+    *slot_out = slot;
+    return KBC_OK;
+}
+
+int kbc_pool_advance(kbc_pool_handle p, int64_t g)
+{
+    if (int r = check_pool(p)) return r;
+    if (g < 1 || g > 4096) return pfail(KBC_EINVAL, "g must be in [1, 4096]");
+    PHIP(hipSetDevice(p->device));
+    tuner_collect(p, false);
+    LaunchCfg cfg = p->cfg;
+    int cand = -1;
+    if (p->tuning && !p->timing_pending && p->cand_next < p->cands.size()) {
+        cand = (int)p->cand_next++;
+        cfg = p->cands[cand];
+    }
+    // per-group box tables for this batch
+    const int m = p->mirror;
+    if (p->mirror_used[m]) PHIP(hipEventSynchronize(p->mirror_ev[m]));
+    uint32_t count[2] = {0, 0}, tiles[2] = {0, 0};
+    int64_t batch = 0;
+    double node_steps = 0.0;
+    for (auto& s : p->slots) {
+        if (!s.used || s.t >= s.target) continue;
+        const int64_t steps = std::min<int64_t>(g, s.target - s.t);
+        const int grp = (int)(s.t & 1);
+        PoolBox& b = p->h_boxes[m][grp][count[grp]++];
+        b.buf = p->arena_base + s.off;
+        b.g = s.g;
+        b.c = s.c;
+        b.tile0 = tiles[grp];
+        b.ntiles = (s.g.nnodes + cfg.block - 1) / cfg.block;
+        b.parity0 = (int32_t)(s.t & 1);
+        b.steps = (int32_t)steps;
+        std::memcpy(b.scale, s.scale, sizeof(b.scale));
+        std::memcpy(b.inv_scale, s.inv_scale, sizeof(b.inv_scale));
+        tiles[grp] += b.ntiles;
+        batch = std::max(batch, steps);
+        node_steps += (double)s.g.nnodes * (double)steps;
+    }
+    if (batch == 0) return KBC_OK;
+    for (int grp = 0; grp < 2; ++grp) {
+        PoolMeta& mt = *p->h_meta[m][grp];
+        mt.n_active = count[grp];
+        mt.n_tiles = tiles[grp];
+        mt.tile_nodes = (uint32_t)cfg.block;
+        mt.pad_ = 0;
+        if (count[grp])
+            PHIP(hipMemcpyAsync(p->d_boxes[grp], p->h_boxes[m][grp], count[grp] * sizeof(PoolBox),
+                                hipMemcpyHostToDevice, p->stream));
+        PHIP(hipMemcpyAsync(p->d_meta[grp], p->h_meta[m][grp], sizeof(PoolMeta), hipMemcpyHostToDevice,
+                            p->stream));
+    }
+    PHIP(hipEventRecord(p->mirror_ev[m], p->stream));
+    p->mirror_used[m] = true;
+    p->mirror = 1 - m;
+
+    hipGraphExec_t exec = nullptr;
+    if (int r = get_graph(p, batch, cfg, &exec)) return r;
+    if (cand >= 0) PHIP(hipEventRecord(p->tev0, p->stream));
+    PHIP(hipGraphLaunch(exec, p->stream));
+    if (cand >= 0) {
+        PHIP(hipEventRecord(p->tev1, p->stream));
+        p->timing_pending = true;
+        p->timing_cand = cand;
+        p->timing_node_steps = node_steps;
+    }
+    auto ev = std::make_shared<Event>();
+    PHIP(hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
+    PHIP(hipEventRecord(ev->e, p->stream));
+    for (auto& s : p->slots) {
+        if (!s.used || s.t >= s.target) continue;
+        s.t_prev = s.t;
+        s.t += std::min<int64_t>(g, s.target - s.t);
+        s.last = ev;
+    }
+    return KBC_OK;
+}
+
+int kbc_pool_poll(kbc_pool_handle p, int32_t slot, int64_t* remaining)
+{
+    if (int r = check_slot(p, slot)) return r;
+    if (!remaining) return pfail(KBC_EINVAL, "remaining is NULL");
+    const Slot& s = p->slots[slot];
+    const int64_t completed = (!s.last || s.last->done()) ? s.t : s.t_prev;
+    *remaining = s.target - completed;
+    return KBC_OK;
+}
+
+int kbc_pool_result(kbc_pool_handle p, int32_t slot, double* k, double* omega, double* rho, double* u)
+{
+    if (int r = check_slot(p, slot)) return r;
+    Slot& s = p->slots[slot];
+    if (s.t < s.target) return pfail(KBC_ESTATE, "the box has steps left to run");
+    PHIP(hipSetDevice(p->device));
+    if (int r = ensure_diag(p, s.g.nnodes)) return r;
+    if (s.last) PHIP(hipStreamWaitEvent(p->diag_stream, s.last->e, 0));
+    const void* buf = p->arena_base + s.off;
+    const int layout = (s.t % 2 == 0) ? LY_AA_EVEN : LY_AA_ODD;
+    const int storage = p->dtype == KBC_F32_DEV_X ? KBC_F32_DEV : p->dtype;
+    PHIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), p->diag_stream));
+    PHIP(launch_moments(storage, layout, buf, s.g, s.inv_scale, p->d_rho, p->d_u, p->d_flag,
+                        p->diag_stream));
+    PHIP(launch_reduce(0, s.g, p->d_u, nullptr, p->d_partial, p->d_sum, p->diag_stream));
+    PHIP(launch_reduce(1, s.g, p->d_u, p->d_sum, p->d_partial, p->d_sum + 3, p->diag_stream));
+    PHIP(launch_reduce(2, s.g, p->d_u, p->d_sum, p->d_partial, p->d_sum + 6, p->diag_stream));
+    double sums[8];
+    int flag = 0;
+    PHIP(hipMemcpyAsync(sums, p->d_sum, sizeof(sums), hipMemcpyDeviceToHost, p->diag_stream));
+    PHIP(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, p->diag_stream));
+    PHIP(hipStreamSynchronize(p->diag_stream));
+    const double N = (double)s.g.nnodes;
+    if (k) *k = 0.5 * sums[3] / N;
+    if (omega) *omega = 0.5 * sums[6] / N;
+    if (rho) PHIP(hipMemcpy(rho, p->d_rho, s.g.nnodes * sizeof(double), hipMemcpyDeviceToHost));
+    if (u) PHIP(hipMemcpy(u, p->d_u, 3ull * s.g.nnodes * sizeof(double), hipMemcpyDeviceToHost));
+    if (flag) return pfail(KBC_EUNSTABLE, "the box's state is not finite (its run diverged)");
+    return KBC_OK;
+}
+
+int kbc_pool_release(kbc_pool_handle p, int32_t slot)
+{
+    if (int r = check_slot(p, slot)) return r;
+    Slot& s = p->slots[slot];
+    if (s.last) PHIP(hipEventSynchronize(s.last->e));
+    if (s.t < s.target) {
+        // cancelled while unfinished: no later batch may still refer to it
+        PHIP(hipStreamSynchronize(p->stream));
+    }
+    PHIP(hipStreamSynchronize(p->diag_stream));
+    p->arena.release(s.off, s.bytes);
+    s = Slot();
+    return KBC_OK;
+}
+
+int kbc_pool_sync(kbc_pool_handle p)
+{
+    if (int r = check_pool(p)) return r;
+    PHIP(hipSetDevice(p->device));
+    PHIP(hipStreamSynchronize(p->stream));
+    tuner_collect(p, true);
+    return KBC_OK;
+}
+
+int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t* block, int32_t* grid,
+                  int32_t* tuning)
+{
+    if (int r = check_pool(p)) return r;
+    int32_t n = 0;
+    for (auto& s : p->slots) n += s.used ? 1 : 0;
+    if (bytes_used) *bytes_used = p->arena.used();
+    if (boxes) *boxes = n;
+    if (block) *block = p->cfg.block;
+    if (grid) *grid = p->cfg.grid;
+    if (tuning) *tuning = p->tuning ? 1 : 0;
+    return KBC_OK;
+}
+
+int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid)
+{
+    if (int r = check_pool(p)) return r;
+    if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 1)
+        return pfail(KBC_EINVAL, "block must be 64..512 in steps of 64 and grid >= 1");
+    p->cfg = LaunchCfg{block, grid};
+    p->tuning = false;
+    return KBC_OK;
+}
+
+}  // extern "C"

@@ -87,6 +87,24 @@ def load():
         "kbc_stream": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_void_p)]),
         "kbc_hbm_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+        "kbc_pool_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32,
+                                           ctypes.POINTER(kbc_options), ctypes.c_int32,
+                                           ctypes.c_char_p, ctypes.POINTER(_H)]),
+        "kbc_pool_destroy": (ctypes.c_int, [_H]),
+        "kbc_pool_admit": (ctypes.c_int, [_H, I64P, ctypes.c_double, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+        "kbc_pool_advance": (ctypes.c_int, [_H, ctypes.c_int64]),
+        "kbc_pool_poll": (ctypes.c_int, [_H, ctypes.c_int32, I64P]),
+        "kbc_pool_result": (ctypes.c_int, [_H, ctypes.c_int32, _D, _D, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+        "kbc_pool_release": (ctypes.c_int, [_H, ctypes.c_int32]),
+        "kbc_pool_sync": (ctypes.c_int, [_H]),
+        "kbc_pool_info": (ctypes.c_int, [_H, ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+        "kbc_pool_set_launch": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32]),
         "kbc_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -210,6 +228,68 @@ def kbc_hbm_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0):
     _check(load().kbc_hbm_copy(dst_ptr, src_ptr, int(nbytes), stream or None), "kbc_hbm_copy")
 
 
+def kbc_pool_create(budget_bytes: int, dtype: int = F32_DEV_X, opt: kbc_options | None = None,
+                    max_slots: int = 256, tune_cache: str | None = None) -> int:
+    h = _H()
+    _check(load().kbc_pool_create(int(budget_bytes), int(dtype),
+                                  ctypes.byref(opt) if opt is not None else None, int(max_slots),
+                                  tune_cache.encode() if tune_cache else None, ctypes.byref(h)),
+           "kbc_pool_create")
+    return h.value
+
+
+def kbc_pool_destroy(p: int):
+    _check(load().kbc_pool_destroy(p), "kbc_pool_destroy")
+
+
+def kbc_pool_admit(p: int, shape, nu: float, u, steps: int) -> int:
+    s = (ctypes.c_int64 * 3)(*[int(v) for v in shape])
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    slot = ctypes.c_int32()
+    _check(load().kbc_pool_admit(p, s, float(nu), _p(u), int(steps), ctypes.byref(slot)),
+           "kbc_pool_admit")
+    return slot.value
+
+
+def kbc_pool_advance(p: int, g: int):
+    _check(load().kbc_pool_advance(p, int(g)), "kbc_pool_advance")
+
+
+def kbc_pool_poll(p: int, slot: int) -> int:
+    r = ctypes.c_int64()
+    _check(load().kbc_pool_poll(p, int(slot), ctypes.byref(r)), "kbc_pool_poll")
+    return r.value
+
+
+def kbc_pool_result(p: int, slot: int, rho_out=None, u_out=None):
+    k = ctypes.c_double()
+    w = ctypes.c_double()
+    _check(load().kbc_pool_result(p, int(slot), ctypes.byref(k), ctypes.byref(w), _p(rho_out),
+                                  _p(u_out)), "kbc_pool_result")
+    return k.value, w.value
+
+
+def kbc_pool_release(p: int, slot: int):
+    _check(load().kbc_pool_release(p, int(slot)), "kbc_pool_release")
+
+
+def kbc_pool_sync(p: int):
+    _check(load().kbc_pool_sync(p), "kbc_pool_sync")
+
+
+def kbc_pool_info(p: int) -> dict:
+    used = ctypes.c_size_t()
+    boxes, block, grid, tuning = (ctypes.c_int32() for _ in range(4))
+    _check(load().kbc_pool_info(p, ctypes.byref(used), ctypes.byref(boxes), ctypes.byref(block),
+                                ctypes.byref(grid), ctypes.byref(tuning)), "kbc_pool_info")
+    return {"bytes_used": used.value, "boxes": boxes.value, "block": block.value,
+            "grid": grid.value, "tuning": bool(tuning.value)}
+
+
+def kbc_pool_set_launch(p: int, block: int, grid: int):
+    _check(load().kbc_pool_set_launch(p, int(block), int(grid)), "kbc_pool_set_launch")
+
+
 def kbc_last_error() -> str:
     return load().kbc_last_error().decode()
 
@@ -310,9 +390,76 @@ class Box:
             pass
 
 
+class Pool:
+    """A batched ensemble of boxes on one GPU (continuous batching)."""
+
+    def __init__(self, budget_bytes, dtype=F32_DEV_X, variant=S_DTQ, max_slots=256,
+                 tune_cache=None, gamma=None, device=-1, stream=None):
+        if isinstance(dtype, str):
+            dtype = DTYPES[dtype]
+        o = kbc_options_default()
+        o.variant = variant
+        o.gamma_fixed = 0 if gamma is None else 1
+        o.gamma_value = 2.0 if gamma is None else float(gamma)
+        o.device = device
+        o.stream = stream
+        self.dtype = dtype
+        self.h = kbc_pool_create(budget_bytes, dtype, o, max_slots, tune_cache)
+
+    def admit(self, u, nu, steps) -> int:
+        """u: [3][nz][ny][nx]; returns the slot."""
+        nz, ny, nx = u.shape[1:]
+        return kbc_pool_admit(self.h, (nx, ny, nz), nu, u, steps)
+
+    def advance(self, g):
+        kbc_pool_advance(self.h, g)
+
+    def poll(self, slot) -> int:
+        return kbc_pool_poll(self.h, slot)
+
+    def result(self, slot, shape=None):
+        """(k, Omega) or, with shape=(nx, ny, nz), (k, Omega, rho, u)."""
+        if shape is None:
+            return kbc_pool_result(self.h, slot)
+        nx, ny, nz = shape
+        rho = np.empty((nz, ny, nx))
+        u = np.empty((3, nz, ny, nx))
+        k, w = kbc_pool_result(self.h, slot, rho, u)
+        return k, w, rho, u
+
+    def release(self, slot):
+        kbc_pool_release(self.h, slot)
+
+    def sync(self):
+        kbc_pool_sync(self.h)
+
+    def info(self) -> dict:
+        return kbc_pool_info(self.h)
+
+    def set_launch(self, block, grid):
+        kbc_pool_set_launch(self.h, block, grid)
+
+    def close(self):
+        if getattr(self, "h", None):
+            kbc_pool_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def beta_from_nu(nu: float) -> float:
     """beta = 1/(6 nu + 1): the viscosity relation the library applies."""
     return 1.0 / (6.0 * nu + 1.0)
 
 
-__all__ = [n for n in dir() if n.startswith("kbc_")] + ["Box", "KbcError", "load"]
+__all__ = [n for n in dir() if n.startswith("kbc_")] + ["Box", "Pool", "KbcError", "load"]

@@ -120,3 +120,14 @@ def test_fast_division_host_check():
                        check=True)
         r = subprocess.run([exe], capture_output=True, text=True)
         assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_pool_create_rejects_bad_arguments():
+    for budget, dtype, slots in [(1 << 30, 9, 8), (1 << 30, kbc.F32_DEV, 0),
+                                 (1024, kbc.F32_DEV, 8), (1 << 30, kbc.F32_DEV, 70000)]:
+        with pytest.raises(kbc.KbcError) as e:
+            kbc.kbc_pool_create(budget, dtype, None, slots, None)
+        assert e.value.code == kbc.KBC_EINVAL
+    lib = kbc.load()
+    assert lib.kbc_pool_destroy(None) == kbc.KBC_OK
+    assert lib.kbc_pool_advance(None, 1) == kbc.KBC_EINVAL

@@ -1,0 +1,184 @@
+"""GPU tests of the batched ensemble (pool): parity with the oracle, each box
+identical alone and in a mix, HBM-budget admission, failure isolation and
+launch-shape independence."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1507_02518_amd import inputs, kbc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pop_bytes(shape, dtype):
+    return 27 * shape[0] * shape[1] * shape[2] * {kbc.F64: 8, kbc.F16_DEV: 2}.get(dtype, 4)
+
+
+def _alone(shape, nu, u, steps, dtype, gamma=None):
+    with kbc.Box(shape, nu, dtype, streaming=kbc.AA, gamma=gamma) as b:
+        b.init_velocity(u)
+        b.step(steps)
+        rho, uu = b.moments()
+        return b.energy(), b.enstrophy(), rho, uu
+
+
+BOXES = [((13, 9, 7), 3e-4, 7), ((16, 16, 16), 1e-3, 12), ((20, 6, 11), 5e-3, 9),
+         ((8, 8, 8), 2e-4, 1)]
+
+
+def test_pool_boxes_match_oracle(orc):
+    with kbc.Pool(64 << 20, kbc.F64, max_slots=8) as pool:
+        slots = []
+        for i, (shape, nu, steps) in enumerate(BOXES):
+            u = inputs.smooth_random(shape, 0.05, seed=i)
+            slots.append((pool.admit(u, nu, steps), shape, nu, steps, u))
+        for _ in range(4):
+            pool.advance(3)
+        for slot, shape, nu, steps, u in slots:
+            k, w, rho, ug = pool.result(slot, shape)
+            F = orc.run(orc.init_feq(u), orc.beta_from_nu(nu), steps)
+            rho_o, u_o = orc.macros(F)
+            assert np.abs(rho - rho_o).max() <= 1e-14
+            assert np.abs(ug - u_o).max() <= 1e-14
+            assert k == pytest.approx(orc.energy(u_o), rel=1e-12)
+    say("pool vs oracle ok")
+
+
+@pytest.mark.parametrize("dtype", [kbc.F64, kbc.F32_DEV_X, kbc.F16_DEV])
+def test_each_box_is_identical_alone_and_in_the_mix(dtype):
+    """Staggered admissions (boxes join at different times and parities),
+    batches of different lengths: every box equals its own solo run bit for
+    bit."""
+    specs = [((24, 24, 24), 4e-4, 31, 0), ((13, 17, 9), 1e-3, 18, 1), ((32, 32, 32), 2e-4, 25, 2),
+             ((10, 10, 10), 3e-3, 40, 3), ((7, 19, 5), 6e-4, 11, 4)]
+    fields = [inputs.hit(s, 3.0, 0.04, seed=seed) for s, _, _, seed in specs]
+    budget = sum(_pop_bytes(s, dtype) for s, _, _, _ in specs) + (16 << 20)
+    got = {}
+    with kbc.Pool(budget, dtype, max_slots=8) as pool:
+        slot = {}
+        slot[0] = pool.admit(fields[0], specs[0][1], specs[0][2])
+        pool.advance(3)
+        slot[1] = pool.admit(fields[1], specs[1][1], specs[1][2])
+        pool.advance(4)
+        slot[2] = pool.admit(fields[2], specs[2][1], specs[2][2])
+        slot[3] = pool.admit(fields[3], specs[3][1], specs[3][2])
+        pool.advance(5)
+        slot[4] = pool.admit(fields[4], specs[4][1], specs[4][2])
+        for g in (2, 7, 1, 9, 9, 9, 9):
+            pool.advance(g)
+        pool.sync()
+        for i, (s, nu, steps, _) in enumerate(specs):
+            assert pool.poll(slot[i]) == 0
+            got[i] = pool.result(slot[i], s)
+    for i, (s, nu, steps, _) in enumerate(specs):
+        k, w, rho, u = _alone(s, nu, fields[i], steps, dtype)
+        assert got[i][0] == k and got[i][1] == w, (i, got[i][:2], (k, w))
+        assert np.array_equal(got[i][2], rho) and np.array_equal(got[i][3], u), i
+    say(f"alone vs mix dtype={dtype}: bitwise equal")
+
+
+def test_budget_and_slots_bound_admission():
+    s = (16, 16, 16)
+    u = inputs.taylor_green(s, 0.04)
+    one = _pop_bytes(s, kbc.F32_DEV_X)
+    grain = 65536
+    per = (one + grain - 1) // grain * grain
+    with kbc.Pool(2 * per, kbc.F32_DEV_X, max_slots=4) as pool:
+        a = pool.admit(u, 1e-3, 5)
+        b = pool.admit(u, 1e-3, 5)
+        with pytest.raises(kbc.KbcError) as e:
+            pool.admit(u, 1e-3, 5)
+        assert e.value.code == kbc.KBC_ECAPACITY
+        assert pool.info()["bytes_used"] == 2 * per
+        pool.advance(5)
+        pool.result(a)
+        pool.release(a)
+        c = pool.admit(u, 1e-3, 5)
+        assert c == a
+        pool.release(b)
+        pool.release(c)
+        assert pool.info()["bytes_used"] == 0
+    with kbc.Pool(64 << 20, kbc.F32_DEV_X, max_slots=2) as pool:
+        pool.admit(u, 1e-3, 1)
+        pool.admit(u, 1e-3, 1)
+        with pytest.raises(kbc.KbcError) as e:
+            pool.admit(u, 1e-3, 1)
+        assert e.value.code == kbc.KBC_ECAPACITY
+
+
+def test_result_before_the_end_is_a_state_error_and_bad_input_is_rejected():
+    s = (8, 8, 8)
+    u = inputs.taylor_green(s, 0.04)
+    with kbc.Pool(16 << 20, kbc.F32_DEV_X, max_slots=4) as pool:
+        a = pool.admit(u, 1e-3, 10)
+        pool.advance(3)
+        with pytest.raises(kbc.KbcError) as e:
+            pool.result(a)
+        assert e.value.code == kbc.KBC_ESTATE
+        bad = u.copy()
+        bad[0, 1, 1, 1] = 1.5
+        with pytest.raises(kbc.KbcError) as e:
+            pool.admit(bad, 1e-3, 10)
+        assert e.value.code == kbc.KBC_EUNSTABLE
+        assert pool.info()["boxes"] == 1
+
+
+def test_a_diverging_box_does_not_perturb_the_others():
+    """Forced LBGK (gamma = 2): an under-resolved box at tiny viscosity
+    diverges; the resolved box next to it equals its solo run."""
+    s = (16, 16, 16)
+    wild = inputs.hit(s, 2.0, 0.05, seed=0)
+    calm = inputs.taylor_green(s, 0.02)
+    with kbc.Pool(64 << 20, kbc.F64, max_slots=4, gamma=2.0) as pool:
+        a = pool.admit(wild, 1e-5, 300)
+        b = pool.admit(calm, 1e-2, 300)
+        for _ in range(10):
+            pool.advance(30)
+        with pytest.raises(kbc.KbcError) as e:
+            pool.result(a)
+        assert e.value.code == kbc.KBC_EUNSTABLE
+        k, w, rho, u = pool.result(b, s)
+    ka, wa, rhoa, ua = _alone(s, 1e-2, calm, 300, kbc.F64, gamma=2.0)
+    assert k == ka and w == wa and np.array_equal(rho, rhoa) and np.array_equal(u, ua)
+
+
+def test_launch_shape_does_not_change_results_and_tuner_settles():
+    specs = [((24, 24, 24), 4e-4), ((40, 12, 9), 1e-3), ((33, 33, 33), 2e-4)]
+    fields = [inputs.hit(s, 3.0, 0.04, seed=i) for i, (s, _) in enumerate(specs)]
+    outs = []
+    for launch in [(128, 512), (512, 4096), (64, 7)]:
+        with kbc.Pool(256 << 20, kbc.F32_DEV_X, max_slots=4) as pool:
+            pool.set_launch(*launch)
+            slots = [pool.admit(f, nu, 20) for f, (_, nu) in zip(fields, specs)]
+            pool.advance(20)
+            outs.append([pool.result(sl, s) for sl, (s, _) in zip(slots, specs)])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert a[0] == b[0] and np.array_equal(a[3], b[3])
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tune.txt")
+        with kbc.Pool(256 << 20, kbc.F32_DEV_X, max_slots=4, tune_cache=cache) as pool:
+            slots = [pool.admit(f, nu, 400) for f, (_, nu) in zip(fields, specs)]
+            for _ in range(20):
+                pool.advance(20)
+            pool.sync()
+            info = pool.info()
+            assert not info["tuning"]
+            res = [pool.result(sl, s) for sl, (s, _) in zip(slots, specs)]
+        assert os.path.exists(cache)
+        with kbc.Pool(256 << 20, kbc.F32_DEV_X, max_slots=4, tune_cache=cache) as pool:
+            info2 = pool.info()
+            assert not info2["tuning"]
+            assert (info2["block"], info2["grid"]) == (info["block"], info["grid"])
+    for sl_res, (s, nu), f in zip(res, specs, fields):
+        k, w, rho, u = _alone(s, nu, f, 400, kbc.F32_DEV_X)
+        assert sl_res[0] == k and np.array_equal(sl_res[3], u)
+    say(f"tuned launch: block={info['block']} grid={info['grid']}")
