@@ -195,6 +195,11 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
  * steps, g in [1, 4096].  Returns without waiting. */
 int kbc_pool_advance(kbc_pool_handle p, int64_t g);
 
+/* Same, for the listed slots only (count >= 0; the others wait): lets a
+ * scheduler order the work, e.g. shortest remaining work first.  KBC_EINVAL
+ * if a listed slot is empty. */
+int kbc_pool_advance_slots(kbc_pool_handle p, int64_t g, const int32_t* slots, int32_t count);
+
 /* Steps of the box not yet completed on the device (0 = result ready).
  * Does not block. */
 int kbc_pool_poll(kbc_pool_handle p, int32_t slot, int64_t* remaining);
@@ -213,14 +218,15 @@ int kbc_pool_release(kbc_pool_handle p, int32_t slot);
 /* Wait for every enqueued batch. */
 int kbc_pool_sync(kbc_pool_handle p);
 
-/* Arena bytes in use, resident boxes, current launch shape and whether the
- * tuner is still measuring (any pointer may be NULL). */
+/* Arena bytes in use, resident boxes, current launch shape (threads per
+ * block; blocks, 0 meaning one block per tile; block-sized sub-tiles per
+ * tile) and whether the tuner is still measuring (any pointer may be NULL). */
 int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t* block,
-                  int32_t* grid, int32_t* tuning);
+                  int32_t* grid, int32_t* sub, int32_t* tuning);
 
-/* Fix the launch shape (block: 64..512 in steps of 64; grid >= 1) and stop
- * tuning. */
-int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid);
+/* Fix the launch shape (block: 64..512 in steps of 64; grid >= 0, 0 for
+ * one block per tile; sub in 1..64) and stop tuning. */
+int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid, int32_t sub);
 
 /* Measurement utility (not part of the method): copy `bytes` (a multiple of
  * 16) from device src to device dst with a plain streaming kernel on the

@@ -78,7 +78,7 @@ struct PoolBox {
     Geom g;
     Coll c;
     uint32_t tile0;       // first tile of the box in the current batch
-    uint32_t ntiles;      // ceil(nnodes / tile_nodes)
+    uint32_t ntiles;      // ceil(nnodes / (block * sub))
     int32_t parity0;      // t mod 2 at the start of the batch
     int32_t steps;        // steps the box takes in the current batch
     float scale[27], inv_scale[27];
@@ -87,8 +87,8 @@ struct PoolBox {
 struct PoolMeta {
     uint32_t n_active;    // boxes in the table, sorted by tile0
     uint32_t n_tiles;     // total tiles
-    uint32_t tile_nodes;  // nodes per tile (= threads per block)
-    uint32_t pad_;
+    uint32_t block;       // threads per block
+    uint32_t sub;         // block-sized sub-tiles per tile
 };
 
 constexpr int kPoolMaxBlock = 512;
@@ -96,7 +96,9 @@ constexpr int kPoolMaxBlock = 512;
 // Step k (0-based) of a batch for one parity group: every box of the table
 // with k < steps applies the AA sweep `sweep` (SW_AA_EVEN or SW_AA_ODD).
 // Persistent grid-stride loop over the group's tiles; block <= 512.
+// tstart[b] = boxes[b].tile0, a compact copy for the tile -> box search.
 hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
-                            const PoolMeta* meta, int k, int block, int grid, hipStream_t stream);
+                            const uint32_t* tstart, const PoolMeta* meta, int k, int block,
+                            int grid, hipStream_t stream);
 
 }  // namespace kbc

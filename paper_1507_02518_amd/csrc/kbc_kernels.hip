@@ -91,9 +91,10 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 
     if constexpr (SW != SW_PULL) {
         // AA sweeps read and write the same 27 locations through src and
-        // dst (one buffer): every load is issued before any store, and the
-        // compiler may not move memory accesses across this point
-        asm volatile("" ::: "memory");
+        // dst (one buffer): the instruction scheduler may not move any
+        // instruction across this point, so every load is issued before any
+        // store (checked on the built code by the test suite)
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     collide<S, V>(f, c);
@@ -143,48 +144,61 @@ k_step(StepParams p)
     node_update<S, V, SW>(p.src, p.dst, p.g, p.c, p.scale, p.inv_scale, n);
 }
 
+typedef __attribute__((address_space(1))) char gchar;
+
 // Batched step over one parity group of a pool's boxes (AA sweep SW, in
-// place).  Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; a
-// tile belongs to the last box whose first tile is not after it (binary
-// search over the table, sorted by first tile).  Boxes are disjoint in
-// memory and each node is updated by exactly one thread, so a box evolves
-// exactly as it would alone.
+// place).  A tile is `sub` consecutive block-sized runs of one box's nodes.
+// Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; a tile
+// belongs to the last box whose first tile is not after it (binary search
+// over the compact array of first tiles).  Boxes are disjoint in memory and
+// each node is updated by exactly one thread, so a box evolves exactly as it
+// would alone.
 template <int S, int V, int SW>
 __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ boxes,
+                                                             const uint32_t* __restrict__ tstart,
                                                              const PoolMeta* __restrict__ meta,
                                                              int k)
 {
     const uint32_t n_tiles = meta->n_tiles;
     const uint32_t n_active = meta->n_active;
-    const uint32_t tn = meta->tile_nodes;
+    const uint32_t block = meta->block;
+    const uint32_t sub = meta->sub;
 #pragma unroll 1
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         uint32_t lo = 0, hi = n_active;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (boxes[mid].tile0 <= tile) lo = mid;
+            if (tstart[mid] <= tile) lo = mid;
             else hi = mid;
         }
         const PoolBox& b = boxes[lo];
+        if (k >= b.steps) continue;
         // the box's constants as values, so the population stores cannot be
         // taken to alias them
         const Geom g = b.g;
         const Coll c = b.c;
-        void* const buf = b.buf;
-        const int steps = b.steps;
-        const uint32_t n = (tile - b.tile0) * tn + threadIdx.x;
-        if (k < steps && n < g.nnodes) {
-            // the store side sees the buffer through a second pointer, as in
-            // the single-box kernel (loads and stores are kept apart by the
-            // barrier in node_update)
-            void* dbuf = buf;
-            asm volatile("" : "+s"(dbuf));
-            node_update<S, V, SW>(buf, dbuf, g, c, b.scale, b.inv_scale, n);
+        // the table holds a generic pointer; it addresses global memory, and
+        // saying so lets the compiler use global (not flat) loads and stores
+        gchar* const gbuf = (gchar*)b.buf;
+        const uint32_t first = (tile - tstart[lo]) * sub * block;
+#pragma unroll 1
+        for (uint32_t r = 0; r < sub; ++r) {
+            const uint32_t n = first + r * block + threadIdx.x;
+            if (n < g.nnodes) {
+                // loads and stores see the buffer through two global pointers,
+                // as in the single-box kernel (they are kept apart by the
+                // scheduling barrier in node_update)
+                gchar* sbuf = gbuf;
+                gchar* dbuf = gbuf;
+                asm volatile("" : "+s"(sbuf));
+                asm volatile("" : "+s"(dbuf));
+                node_update<S, V, SW>((void*)sbuf, (void*)dbuf, g, c, b.scale, b.inv_scale, n);
+            }
         }
     }
 }
 
-using PoolFn = void (*)(const PoolBox*, const PoolMeta*, int);
+using PoolFn = void (*)(const PoolBox*, const uint32_t*, const PoolMeta*, int);
 
 template <int S, int V>
 PoolFn pool_fn_sw(int sw)
@@ -580,7 +594,8 @@ hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
 }
 
 hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
-                            const PoolMeta* meta, int k, int block, int grid, hipStream_t stream)
+                            const uint32_t* tstart, const PoolMeta* meta, int k, int block,
+                            int grid, hipStream_t stream)
 {
     if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 1) return hipErrorInvalidValue;
     if (sweep != SW_AA_EVEN && sweep != SW_AA_ODD) return hipErrorInvalidValue;
@@ -591,7 +606,7 @@ hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* 
     case ST_F32X: fn = pool_fn_v<ST_F32X>(variant, sweep); break;
     default: fn = pool_fn_v<ST_F16>(variant, sweep); break;
     }
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, boxes, meta, k);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, boxes, tstart, meta, k);
     return hipGetLastError();
 }
 

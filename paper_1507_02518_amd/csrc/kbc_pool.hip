@@ -128,8 +128,17 @@ struct Slot {
 };
 
 struct LaunchCfg {
-    int block, grid;
+    int block, grid, sub;   // threads per block, blocks (0: one per tile), sub-tiles per tile
 };
+
+// Blocks of a launch: the persistent grid, or one block per tile rounded up
+// to a multiple of 2048 (few distinct graphs; spare blocks exit at once).
+int launch_grid(const LaunchCfg& cfg, uint32_t tiles)
+{
+    if (cfg.grid > 0) return cfg.grid;
+    const uint32_t t = std::max<uint32_t>(tiles, 1);
+    return (int)((t + 2047) / 2048 * 2048);
+}
 
 }  // namespace
 
@@ -143,14 +152,16 @@ struct kbc_pool {
     std::vector<Slot> slots;
     PoolBox* d_boxes[2] = {nullptr, nullptr};
     PoolMeta* d_meta[2] = {nullptr, nullptr};
+    uint32_t* d_tstart[2] = {nullptr, nullptr};
     PoolBox* h_boxes[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     PoolMeta* h_meta[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint32_t* h_tstart[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipEvent_t mirror_ev[2] = {nullptr, nullptr};
     bool mirror_used[2] = {false, false};
     int mirror = 0;
     std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;
     std::vector<std::tuple<int64_t, int, int>> graph_order;
-    LaunchCfg cfg{256, 1024};
+    LaunchCfg cfg{256, 1024, 4};
     bool tuning = false;
     std::vector<LaunchCfg> cands;
     std::vector<double> cand_cost;
@@ -217,8 +228,10 @@ void load_tune_cache(kbc_pool* p)
         if (bar == std::string::npos || line.substr(0, bar) != key) continue;
         std::istringstream rest(line.substr(bar + 1));
         int block = 0, grid = 0;
-        if (rest >> block >> grid && block >= 64 && block <= kPoolMaxBlock && block % 64 == 0 && grid > 0) {
-            p->cfg = LaunchCfg{block, grid};
+        int sub = 0;
+        if (rest >> block >> grid >> sub && block >= 64 && block <= kPoolMaxBlock && block % 64 == 0 &&
+            grid >= 0 && sub >= 1 && sub <= 64) {
+            p->cfg = LaunchCfg{block, grid, sub};
             p->tuning = false;
         }
     }
@@ -236,7 +249,7 @@ void save_tune_cache(kbc_pool* p)
     }
     std::ofstream out(p->tune_cache, std::ios::trunc);
     for (auto& l : keep) out << l << "\n";
-    out << cache_key(p) << "|" << p->cfg.block << " " << p->cfg.grid << "\n";
+    out << cache_key(p) << "|" << p->cfg.block << " " << p->cfg.grid << " " << p->cfg.sub << "\n";
 }
 
 // Collect a finished timing measurement of the online tuner, if any.
@@ -271,6 +284,7 @@ void destroy_graphs(kbc_pool* p)
 
 int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, hipGraphExec_t* out)
 {
+    // the sub-tile count lives in the uploaded table, not in the graph
     const auto key = std::make_tuple(steps, cfg.block, cfg.grid);
     auto it = p->graphs.find(key);
     if (it != p->graphs.end()) {
@@ -289,11 +303,11 @@ int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, hipGraphExec_t* out)
     for (int64_t k = 0; k < steps && err == hipSuccess; ++k) {
         // group (k mod 2) is at even parity at step k, the other group odd
         const int ge = (int)(k & 1), go = 1 - ge;
-        err = launch_pool_step(p->dtype, p->variant, SW_AA_EVEN, p->d_boxes[ge], p->d_meta[ge], (int)k,
-                               cfg.block, cfg.grid, p->stream);
+        err = launch_pool_step(p->dtype, p->variant, SW_AA_EVEN, p->d_boxes[ge], p->d_tstart[ge],
+                               p->d_meta[ge], (int)k, cfg.block, cfg.grid, p->stream);
         if (err == hipSuccess)
-            err = launch_pool_step(p->dtype, p->variant, SW_AA_ODD, p->d_boxes[go], p->d_meta[go],
-                                   (int)k, cfg.block, cfg.grid, p->stream);
+            err = launch_pool_step(p->dtype, p->variant, SW_AA_ODD, p->d_boxes[go], p->d_tstart[go],
+                                   p->d_meta[go], (int)k, cfg.block, cfg.grid, p->stream);
     }
     const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
     if (err != hipSuccess) {
@@ -359,7 +373,7 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
         p->cus = prop.multiProcessorCount;
-    p->cfg = LaunchCfg{256, 4 * p->cus};
+    p->cfg = LaunchCfg{256, 0, 1};
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {
@@ -378,9 +392,12 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
     for (int grp = 0; grp < 2; ++grp) {
         hipError_t e = hipMalloc(&p->d_boxes[grp], (size_t)max_slots * sizeof(PoolBox));
         if (e == hipSuccess) e = hipMalloc(&p->d_meta[grp], sizeof(PoolMeta));
+        if (e == hipSuccess) e = hipMalloc(&p->d_tstart[grp], (size_t)max_slots * sizeof(uint32_t));
         for (int m = 0; m < 2 && e == hipSuccess; ++m) {
             e = hipHostMalloc((void**)&p->h_boxes[m][grp], (size_t)max_slots * sizeof(PoolBox));
             if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_meta[m][grp], sizeof(PoolMeta));
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&p->h_tstart[m][grp], (size_t)max_slots * sizeof(uint32_t));
         }
         if (e != hipSuccess) {
             kbc_pool_destroy(p.release());
@@ -400,9 +417,11 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
         kbc_pool_destroy(p.release());
         return phip(e, "pool scratch");
     }
-    // tuner candidates: tile (= block) sizes x persistent grid sizes
-    for (int block : {128, 256, 512})
-        for (int mult : {2, 4, 8, 16}) p->cands.push_back(LaunchCfg{block, mult * p->cus});
+    // tuner candidates: block sizes x (one block per tile | persistent grid)
+    // x sub-tiles
+    for (int block : {256, 512})
+        for (int mult : {0, 16})
+            for (int sub : {1, 2, 4}) p->cands.push_back(LaunchCfg{block, mult * p->cus, sub});
     p->cand_cost.assign(p->cands.size(), 1e300);
     p->tuning = true;
     if (tune_cache) p->tune_cache = tune_cache;
@@ -423,9 +442,11 @@ int kbc_pool_destroy(kbc_pool_handle p)
     for (int grp = 0; grp < 2; ++grp) {
         if (p->d_boxes[grp]) (void)hipFree(p->d_boxes[grp]);
         if (p->d_meta[grp]) (void)hipFree(p->d_meta[grp]);
+        if (p->d_tstart[grp]) (void)hipFree(p->d_tstart[grp]);
         for (int m = 0; m < 2; ++m) {
             if (p->h_boxes[m][grp]) (void)hipHostFree(p->h_boxes[m][grp]);
             if (p->h_meta[m][grp]) (void)hipHostFree(p->h_meta[m][grp]);
+            if (p->h_tstart[m][grp]) (void)hipHostFree(p->h_tstart[m][grp]);
         }
     }
     for (int m = 0; m < 2; ++m)
@@ -526,34 +547,49 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
     return KBC_OK;
 }
 
-int kbc_pool_advance(kbc_pool_handle p, int64_t g)
+static int pool_advance(kbc_pool_handle p, int64_t g, const int32_t* only, int32_t n_only)
 {
     if (int r = check_pool(p)) return r;
     if (g < 1 || g > 4096) return pfail(KBC_EINVAL, "g must be in [1, 4096]");
+    std::vector<char> pick;
+    if (only) {
+        pick.assign(p->slots.size(), 0);
+        for (int32_t i = 0; i < n_only; ++i) {
+            if (only[i] < 0 || only[i] >= (int32_t)p->slots.size() || !p->slots[only[i]].used)
+                return pfail(KBC_EINVAL, "slot list names an empty slot");
+            pick[only[i]] = 1;
+        }
+    }
     PHIP(hipSetDevice(p->device));
-    tuner_collect(p, false);
+    // while tuning, each batch times one candidate: wait for the previous one
+    tuner_collect(p, p->tuning);
     LaunchCfg cfg = p->cfg;
     int cand = -1;
     if (p->tuning && !p->timing_pending && p->cand_next < p->cands.size()) {
         cand = (int)p->cand_next++;
         cfg = p->cands[cand];
     }
+    const uint32_t tile_nodes = (uint32_t)(cfg.block * cfg.sub);
     // per-group box tables for this batch
     const int m = p->mirror;
     if (p->mirror_used[m]) PHIP(hipEventSynchronize(p->mirror_ev[m]));
     uint32_t count[2] = {0, 0}, tiles[2] = {0, 0};
     int64_t batch = 0;
     double node_steps = 0.0;
-    for (auto& s : p->slots) {
-        if (!s.used || s.t >= s.target) continue;
+    std::vector<int64_t> adv(p->slots.size(), 0);
+    for (size_t si = 0; si < p->slots.size(); ++si) {
+        Slot& s = p->slots[si];
+        if (!s.used || s.t >= s.target || (only && !pick[si])) continue;
         const int64_t steps = std::min<int64_t>(g, s.target - s.t);
         const int grp = (int)(s.t & 1);
-        PoolBox& b = p->h_boxes[m][grp][count[grp]++];
+        PoolBox& b = p->h_boxes[m][grp][count[grp]];
+        p->h_tstart[m][grp][count[grp]] = tiles[grp];
+        ++count[grp];
         b.buf = p->arena_base + s.off;
         b.g = s.g;
         b.c = s.c;
         b.tile0 = tiles[grp];
-        b.ntiles = (s.g.nnodes + cfg.block - 1) / cfg.block;
+        b.ntiles = (s.g.nnodes + tile_nodes - 1) / tile_nodes;
         b.parity0 = (int32_t)(s.t & 1);
         b.steps = (int32_t)steps;
         std::memcpy(b.scale, s.scale, sizeof(b.scale));
@@ -561,17 +597,21 @@ int kbc_pool_advance(kbc_pool_handle p, int64_t g)
         tiles[grp] += b.ntiles;
         batch = std::max(batch, steps);
         node_steps += (double)s.g.nnodes * (double)steps;
+        adv[si] = steps;
     }
     if (batch == 0) return KBC_OK;
     for (int grp = 0; grp < 2; ++grp) {
         PoolMeta& mt = *p->h_meta[m][grp];
         mt.n_active = count[grp];
         mt.n_tiles = tiles[grp];
-        mt.tile_nodes = (uint32_t)cfg.block;
-        mt.pad_ = 0;
-        if (count[grp])
+        mt.block = (uint32_t)cfg.block;
+        mt.sub = (uint32_t)cfg.sub;
+        if (count[grp]) {
             PHIP(hipMemcpyAsync(p->d_boxes[grp], p->h_boxes[m][grp], count[grp] * sizeof(PoolBox),
                                 hipMemcpyHostToDevice, p->stream));
+            PHIP(hipMemcpyAsync(p->d_tstart[grp], p->h_tstart[m][grp], count[grp] * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, p->stream));
+        }
         PHIP(hipMemcpyAsync(p->d_meta[grp], p->h_meta[m][grp], sizeof(PoolMeta), hipMemcpyHostToDevice,
                             p->stream));
     }
@@ -580,7 +620,9 @@ int kbc_pool_advance(kbc_pool_handle p, int64_t g)
     p->mirror = 1 - m;
 
     hipGraphExec_t exec = nullptr;
-    if (int r = get_graph(p, batch, cfg, &exec)) return r;
+    LaunchCfg gcfg = cfg;
+    gcfg.grid = launch_grid(cfg, std::max(tiles[0], tiles[1]));
+    if (int r = get_graph(p, batch, gcfg, &exec)) return r;
     if (cand >= 0) PHIP(hipEventRecord(p->tev0, p->stream));
     PHIP(hipGraphLaunch(exec, p->stream));
     if (cand >= 0) {
@@ -592,13 +634,23 @@ int kbc_pool_advance(kbc_pool_handle p, int64_t g)
     auto ev = std::make_shared<Event>();
     PHIP(hipEventCreateWithFlags(&ev->e, hipEventDisableTiming));
     PHIP(hipEventRecord(ev->e, p->stream));
-    for (auto& s : p->slots) {
-        if (!s.used || s.t >= s.target) continue;
+    for (size_t si = 0; si < p->slots.size(); ++si) {
+        if (!adv[si]) continue;
+        Slot& s = p->slots[si];
         s.t_prev = s.t;
-        s.t += std::min<int64_t>(g, s.target - s.t);
+        s.t += adv[si];
         s.last = ev;
     }
     return KBC_OK;
+}
+
+int kbc_pool_advance(kbc_pool_handle p, int64_t g) { return pool_advance(p, g, nullptr, 0); }
+
+int kbc_pool_advance_slots(kbc_pool_handle p, int64_t g, const int32_t* slots, int32_t count)
+{
+    if (count < 0 || (count > 0 && !slots)) return pfail(KBC_EINVAL, "bad slot list");
+    if (count == 0) return check_pool(p);
+    return pool_advance(p, g, slots, count);
 }
 
 int kbc_pool_poll(kbc_pool_handle p, int32_t slot, int64_t* remaining)
@@ -667,7 +719,7 @@ int kbc_pool_sync(kbc_pool_handle p)
 }
 
 int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t* block, int32_t* grid,
-                  int32_t* tuning)
+                  int32_t* sub, int32_t* tuning)
 {
     if (int r = check_pool(p)) return r;
     int32_t n = 0;
@@ -676,16 +728,18 @@ int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t
     if (boxes) *boxes = n;
     if (block) *block = p->cfg.block;
     if (grid) *grid = p->cfg.grid;
+    if (sub) *sub = p->cfg.sub;
     if (tuning) *tuning = p->tuning ? 1 : 0;
     return KBC_OK;
 }
 
-int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid)
+int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid, int32_t sub)
 {
     if (int r = check_pool(p)) return r;
-    if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 1)
-        return pfail(KBC_EINVAL, "block must be 64..512 in steps of 64 and grid >= 1");
-    p->cfg = LaunchCfg{block, grid};
+    if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 0 || sub < 1 || sub > 64)
+        return pfail(KBC_EINVAL, "block must be 64..512 in steps of 64, grid >= 0, sub in 1..64");
+    tuner_collect(p, true);
+    p->cfg = LaunchCfg{block, grid, sub};
     p->tuning = false;
     return KBC_OK;
 }

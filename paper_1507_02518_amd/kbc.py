@@ -94,6 +94,8 @@ def load():
         "kbc_pool_admit": (ctypes.c_int, [_H, I64P, ctypes.c_double, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
         "kbc_pool_advance": (ctypes.c_int, [_H, ctypes.c_int64]),
+        "kbc_pool_advance_slots": (ctypes.c_int, [_H, ctypes.c_int64, ctypes.c_void_p,
+                                                  ctypes.c_int32]),
         "kbc_pool_poll": (ctypes.c_int, [_H, ctypes.c_int32, I64P]),
         "kbc_pool_result": (ctypes.c_int, [_H, ctypes.c_int32, _D, _D, ctypes.c_void_p,
                                            ctypes.c_void_p]),
@@ -103,8 +105,10 @@ def load():
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32)]),
-        "kbc_pool_set_launch": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32]),
+        "kbc_pool_set_launch": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32]),
         "kbc_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -255,6 +259,12 @@ def kbc_pool_advance(p: int, g: int):
     _check(load().kbc_pool_advance(p, int(g)), "kbc_pool_advance")
 
 
+def kbc_pool_advance_slots(p: int, g: int, slots):
+    arr = np.ascontiguousarray(slots, dtype=np.int32)
+    _check(load().kbc_pool_advance_slots(p, int(g), _p(arr) if arr.size else None, arr.size),
+           "kbc_pool_advance_slots")
+
+
 def kbc_pool_poll(p: int, slot: int) -> int:
     r = ctypes.c_int64()
     _check(load().kbc_pool_poll(p, int(slot), ctypes.byref(r)), "kbc_pool_poll")
@@ -279,15 +289,16 @@ def kbc_pool_sync(p: int):
 
 def kbc_pool_info(p: int) -> dict:
     used = ctypes.c_size_t()
-    boxes, block, grid, tuning = (ctypes.c_int32() for _ in range(4))
+    boxes, block, grid, sub, tuning = (ctypes.c_int32() for _ in range(5))
     _check(load().kbc_pool_info(p, ctypes.byref(used), ctypes.byref(boxes), ctypes.byref(block),
-                                ctypes.byref(grid), ctypes.byref(tuning)), "kbc_pool_info")
+                                ctypes.byref(grid), ctypes.byref(sub), ctypes.byref(tuning)),
+           "kbc_pool_info")
     return {"bytes_used": used.value, "boxes": boxes.value, "block": block.value,
-            "grid": grid.value, "tuning": bool(tuning.value)}
+            "grid": grid.value, "sub": sub.value, "tuning": bool(tuning.value)}
 
 
-def kbc_pool_set_launch(p: int, block: int, grid: int):
-    _check(load().kbc_pool_set_launch(p, int(block), int(grid)), "kbc_pool_set_launch")
+def kbc_pool_set_launch(p: int, block: int, grid: int, sub: int = 4):
+    _check(load().kbc_pool_set_launch(p, int(block), int(grid), int(sub)), "kbc_pool_set_launch")
 
 
 def kbc_last_error() -> str:
@@ -411,8 +422,11 @@ class Pool:
         nz, ny, nx = u.shape[1:]
         return kbc_pool_admit(self.h, (nx, ny, nz), nu, u, steps)
 
-    def advance(self, g):
-        kbc_pool_advance(self.h, g)
+    def advance(self, g, slots=None):
+        if slots is None:
+            kbc_pool_advance(self.h, g)
+        else:
+            kbc_pool_advance_slots(self.h, g, list(slots))
 
     def poll(self, slot) -> int:
         return kbc_pool_poll(self.h, slot)
@@ -436,8 +450,8 @@ class Pool:
     def info(self) -> dict:
         return kbc_pool_info(self.h)
 
-    def set_launch(self, block, grid):
-        kbc_pool_set_launch(self.h, block, grid)
+    def set_launch(self, block, grid, sub=4):
+        kbc_pool_set_launch(self.h, block, grid, sub)
 
     def close(self):
         if getattr(self, "h", None):

@@ -115,10 +115,18 @@ def _percentiles(lat):
 
 
 def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=1024,
-                tune_cache=None, log=None):
-    """Continuous batching over wall-clock arrivals."""
+                tune_cache=None, log=None, policy="srpt", min_nodes=32 << 20):
+    """Continuous batching over wall-clock arrivals.
+
+    policy "all": every resident box advances in every batch (processor
+    sharing).  policy "srpt": each batch advances the resident boxes with the
+    least remaining work (nodes x steps left) first, adding boxes until the
+    batch holds at least `min_nodes` nodes, enough to fill the GPU; the
+    others wait, which lets short requests overtake long ones.
+    """
     pending = list(trace)
     active = {}
+    left = {}
     done = {}
     results = {}
     with kbc.Pool(budget, dtype, max_slots=max_slots, tune_cache=tune_cache) as pool:
@@ -135,17 +143,33 @@ def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=10
                         break
                     raise
                 active[slot] = r
+                left[slot] = r.steps
                 pending.pop(0)
             if not active:
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
                 continue
-            pool.advance(g)
+            runnable = [sl for sl in active if left[sl] > 0]
+            if policy == "srpt":
+                runnable.sort(key=lambda sl: active[sl].nodes * left[sl])
+                chosen, nodes = [], 0
+                for sl in runnable:
+                    chosen.append(sl)
+                    nodes += active[sl].nodes
+                    if nodes >= min_nodes:
+                        break
+            else:
+                chosen = runnable
+            if chosen:
+                pool.advance(g, chosen)
+                for sl in chosen:
+                    left[sl] -= min(g, left[sl])
             # collect finished boxes
             finished = 0
             for slot in list(active):
-                if pool.poll(slot) == 0:
+                if left[slot] == 0 and pool.poll(slot) == 0:
                     r = active.pop(slot)
+                    del left[slot]
                     results[r.rid] = pool.result(slot)
                     pool.release(slot)
                     done[r.rid] = time.perf_counter() - t0

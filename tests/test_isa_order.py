@@ -1,0 +1,84 @@
+"""Static check of the built AA kernels: a node's 27 loads all precede its
+27 stores.  The in-place AA sweeps read and write the same locations through
+two pointers into one buffer, so the order in the generated gfx950 code is
+what makes them race free; this test reads it from the compiler's own
+assembly of our sources."""
+import glob
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1507_02518_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def asm():
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not present")
+    with tempfile.TemporaryDirectory() as d:
+        subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+                        os.path.join(CSRC, "kbc_kernels.hip"), "--offload-device-only",
+                        "-save-temps", "-o", os.path.join(d, "k.o")],
+                       check=True, cwd=d, capture_output=True)
+        path = glob.glob(os.path.join(d, "*gfx950*.s"))[0]
+        return open(path).read()
+
+
+def _kernels(asm, pattern):
+    names = re.findall(r"^(_ZN3kbc\S*" + pattern + r"\S*):", asm, flags=re.M)
+    out = {}
+    for nm in names:
+        i = asm.index(nm + ":")
+        j = asm.index("s_endpgm", i)
+        ops = [ln.split()[0] for ln in asm[i:j].split("\n")
+               if ln.startswith("\t") and ln.strip() and not ln.strip().startswith((".", ";"))]
+        out[nm] = [op for op in ops if op.startswith(("global_load", "global_store",
+                                                     "buffer_load", "buffer_store"))]
+    return out
+
+
+def test_aa_step_kernels_load_everything_before_storing(asm):
+    ks = _kernels(asm, r"k_stepILi\dELi\dELi[12]E")
+    assert len(ks) == 4 * 4 * 2
+    for nm, ops in ks.items():
+        assert len(ops) == 54, (nm, len(ops))
+        first_store = next(i for i, op in enumerate(ops) if "store" in op)
+        assert first_store == 27 and all("store" in op for op in ops[27:]), nm
+
+
+def _blocks(asm, nm):
+    """Vector memory ops of each basic block of a kernel, in listing order."""
+    i = asm.index(nm + ":")
+    j = asm.index("s_endpgm", i)
+    blocks = [[]]
+    for ln in asm[i:j].split("\n")[1:]:
+        t = ln.strip()
+        if re.match(r"^\.LBB\d+_\d+:", t):
+            blocks.append([])
+        elif t.startswith(("global_load", "buffer_load")):
+            blocks[-1].append("L")
+        elif t.startswith(("global_store", "buffer_store")):
+            blocks[-1].append("S")
+    return blocks
+
+
+def test_pool_kernels_load_everything_before_storing(asm):
+    """The pool kernel loops over tiles, so its loads and stores may sit in
+    different basic blocks (the instruction scheduler never moves code
+    between blocks); inside any block no load may follow a store."""
+    names = re.findall(r"^(_ZN3kbc\S*k_pool_stepILi\dELi\dELi[12]E\S*):", asm, flags=re.M)
+    assert len(names) == 4 * 4 * 2
+    for nm in names:
+        blocks = _blocks(asm, nm)
+        seq = [op for b in blocks for op in b]
+        assert seq.count("L") == 27 and seq.count("S") == 27, nm
+        for b in blocks:
+            text = "".join(b)
+            assert "SL" not in text, (nm, text)
