@@ -43,9 +43,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the files that define the step kernel's code (the host API files do not)
+KERNEL_SOURCES = ("kbc_device.h", "kbc_internal.h", "kbc_kernels.hip")
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -160,6 +164,88 @@ def ensemble_and_serving(kbc, args):
     return out
 
 
+def precision_128(kbc, inputs, log):
+    """128^3 decaying HIT (k0 = 4, u_rms = 0.04, nu = 5e-4, seed 1), 2000
+    steps in each storage form: k(t) and Omega(t) every 10 steps against the
+    FP64 path and, where stored, the CPU checker's series."""
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_hit128_series.txt")
+    ref = None
+    if os.path.exists(golden):
+        import numpy as np
+        ref = np.loadtxt(golden)
+    u = inputs.hit(128, 4.0, 0.04, seed=1)
+    out, series = {}, {}
+    for name, dt, st in [("f64_pull", kbc.F64, kbc.PULL), ("f64_aa", kbc.F64, kbc.AA),
+                         ("f32dev_pull", kbc.F32_DEV, kbc.PULL),
+                         ("f32devx_pull", kbc.F32_DEV_X, kbc.PULL),
+                         ("f32devx_aa", kbc.F32_DEV_X, kbc.AA), ("f16dev_aa", kbc.F16_DEV, kbc.AA)]:
+        log(f"[precision] 128^3 {name}")
+        with kbc.Box(128, 5e-4, dt, streaming=st) as b:
+            b.init_velocity(u)
+            ts, ks, ws = [0], [b.energy()], [b.enstrophy()]
+            for t in range(10, 2001, 10):
+                b.step(10)
+                ts.append(t)
+                ks.append(b.energy())
+                ws.append(b.enstrophy())
+        series[name] = (ts, ks, ws)
+    t64, k64, w64 = series["f64_pull"]
+    for name, (ts, ks, ws) in series.items():
+        r = {"k_final": ks[-1], "omega_final": ws[-1],
+             "max_rel_err_k_vs_f64": max(abs(a / b - 1) for a, b in zip(ks, k64)),
+             "max_rel_err_omega_vs_f64": max(abs(a / b - 1) for a, b in zip(ws, w64))}
+        if ref is not None:
+            idx = {int(row[0]): row for row in ref}
+            pts = [(k, w, idx[t]) for t, k, w in zip(ts, ks, ws) if t in idx]
+            r["oracle_points"] = len(pts)
+            r["max_rel_err_k_vs_oracle"] = max(abs(k / row[1] - 1) for k, w, row in pts)
+            r["max_rel_err_omega_vs_oracle"] = max(abs(w / row[2] - 1) for k, w, row in pts)
+        out[name] = r
+    return out
+
+
+def precision_512(kbc, inputs, log, steps=2000):
+    """512^3 decaying HIT (k0 = 8, u_rms = 0.04, nu = 2.5e-4, seed 2),
+    in-place AA, `steps` steps per storage form: MLUPS, HBM rate, energy,
+    enstrophy and the shell spectrum against the FP64 run on the same field."""
+    import torch
+
+    from paper_1507_02518_amd import analysis
+
+    n = 512
+    log("[precision] building the 512^3 field")
+    u = inputs.hit(n, 8.0, 0.04, seed=2)
+    stream = torch.cuda.Stream()
+    out, spec = {}, {}
+    for name, dt in [("f64_aa", kbc.F64), ("f32dev_aa", kbc.F32_DEV),
+                     ("f32devx_aa", kbc.F32_DEV_X), ("f16dev_aa", kbc.F16_DEV)]:
+        log(f"[precision] 512^3 {name}")
+        with kbc.Box(n, 2.5e-4, dt, streaming=kbc.AA, stream=stream.cuda_stream) as b:
+            b.init_velocity(u)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            k, w = b.energy(), b.enstrophy()
+            _, uu = b.moments()
+            spec[name] = analysis.spectrum(uu)
+            del uu
+            bpn = b.bytes_per_node_step()
+        out[name] = {"ms_per_step": ms, "mlups": n ** 3 / (ms * 1e-3) / 1e6,
+                     "algorithmic_GBs": bpn * n ** 3 / (ms * 1e-3) / 1e9, "k_final": k,
+                     "omega_final": w}
+    for name in out:
+        out[name]["rel_err_k_vs_f64"] = abs(out[name]["k_final"] / out["f64_aa"]["k_final"] - 1)
+        out[name]["rel_err_omega_vs_f64"] = abs(out[name]["omega_final"] /
+                                                out["f64_aa"]["omega_final"] - 1)
+        out[name]["spectrum_err_vs_f64"] = analysis.spectrum_error(spec[name], spec["f64_aa"])
+    return out
+
+
 def cpu_baseline(u, steps):
     import oracle
 
@@ -184,6 +270,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-ensemble", dest="ensemble", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--precision", action="store_true",
+                    help="run the storage-precision study (128^3 and 512^3) instead")
+    ap.add_argument("--precision-steps-512", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the KBC box runs on a single MI355X "
@@ -197,6 +286,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     kbc.load()
+
+    if args.precision:
+        res = {"metric": "storage precision: error vs FP64, D3Q27 KBC decaying HIT",
+               "hit128_2000_steps": precision_128(kbc, inputs, log),
+               "hit512": precision_512(kbc, inputs, log, args.precision_steps_512),
+               "steps_512": args.precision_steps_512}
+        print(json.dumps(res), flush=True)
+        return
 
     log(f"[bench] building the 256^3 HIT field (seed {SEED})")
     u = inputs.hit(N, K0, URMS, seed=SEED)

@@ -189,6 +189,10 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     if (!(nu > 0.0) || !std::isfinite(nu)) return fail(KBC_EINVAL, "nu must be finite and > 0");
     if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV && dtype != KBC_F32_DEV_X)
         return fail(KBC_EINVAL, "unknown dtype");
+    // the step kernels address a node inside a direction plane with a 32-bit
+    // byte offset
+    if (nn * (double)elem_bytes(dtype) > 4294967296.0)
+        return fail(KBC_EINVAL, "a direction plane of this box exceeds 4 GiB (FP64: 2^29 nodes at most)");
     if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return fail(KBC_EINVAL, "unknown variant");
     if (opt.streaming != KBC_PULL && opt.streaming != KBC_AA) return fail(KBC_EINVAL, "unknown streaming");
     if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))

@@ -194,15 +194,36 @@ struct DMom {
     R T, Nxz, Nyz, Pxy, Pxz, Pyz, Qxyy, Qxzz, Qxxy, Qyzz, Qxxz, Qyyz, Qxyz;
 };
 
+// Reciprocal and square root: IEEE-exact in FP64; in the FP32 collision the
+// hardware approximations (about 1 ulp), far below that path's own error.
+__host__ __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ float rcp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ float sqrt_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
 // One-dimensional equilibrium marginals of one axis (section II, product
 // form): e[v+1] and de[v+1] = e - W_v, plus m2 - 1/3 where m2 = (2S - 1)/3.
 template <typename R, bool kNoCancel>
 __host__ __device__ __forceinline__ void marginals1d(R u, R (&e)[3], R (&de)[3], R& dm2)
 {
     const R q3 = R(3) * u * u;
-    const R Sq = sqrt(R(1) + q3);
+    const R Sq = sqrt_(R(1) + q3);
     R sm1;  // S - 1, without cancellation where asked
-    if constexpr (kNoCancel) sm1 = q3 / (R(1) + Sq);
+    if constexpr (kNoCancel) sm1 = q3 * rcp_(R(1) + Sq);
     else sm1 = Sq - R(1);
     dm2 = R(2.0 / 3.0) * sm1;
     const R half_u = R(0.5) * u;
@@ -219,7 +240,7 @@ template <typename R>
 __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
 {
     const R pm = e[0] * e[2];
-    const R ip = R(1) / (pm * e[1]);
+    const R ip = rcp_(pm * e[1]);
     ie[1] = pm * ip;
     ie[2] = e[1] * e[0] * ip;
     ie[0] = e[1] * e[2] * ip;
@@ -285,13 +306,15 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
         gamma = (hhd <= c.gamma_eps * rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
     }
 
-    // --- 7. relax: f' = f - beta (2 ds + gamma dh) -------------------------
-    const R beta = R(c.beta);
+    // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
+    // dh = (f - f^eq) - ds as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
+    const R c1 = R(c.beta) * (R(2) - gamma);
+    const R c2 = R(c.beta) * gamma;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const R ds = ds_of(i);
-        const R dh = fneq_of(i) - ds;
-        f[i] = f[i] - beta * (R(2) * ds + gamma * dh);
+        const R fneq = fneq_of(i);
+        f[i] = f[i] - c1 * ds - c2 * fneq;
     }
 }
 
@@ -377,7 +400,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         // rho and u (deviation forms: rho = 1 + sum g, sum v W = 0)
         const R drho = DEV ? M[0][0][0] : M[0][0][0] - R(1);
         const R rho = DEV ? R(1) + drho : M[0][0][0];
-        const R irho = R(1) / rho;
+        const R irho = rcp_(rho);
         const R u[3] = {M[1][0][0] * irho, M[0][1][0] * irho, M[0][0][1] * irho};
 
         // --- 2. one-dimensional equilibrium marginals ----------------------

@@ -61,31 +61,42 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 {
     using T = typename Traits<S>::T;
     using R = typename Traits<S>::R;
+    // Addresses are a per-direction plane base (uniform across the wave, kept
+    // in scalar registers) plus a 32-bit byte offset within the plane; the
+    // host guarantees that a plane is smaller than 4 GiB.
+    constexpr uint32_t EB = sizeof(T);
     uint32_t x, y, z;
     node_xyz(n, g, x, y, z);
+    const uint32_t rowb = g.nx * EB, planexyb = g.ny * g.nx * EB;
     const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
     const uint32_t ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
     const uint32_t zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
-    // coordinate of x - v along each axis, indexed by v + 1
-    const uint32_t bx[3] = {xp, x, xm};
-    const uint32_t byo[3] = {yp * g.nx, y * g.nx, ym * g.nx};
-    const uint32_t bzo[3] = {zp * g.ny * g.nx, z * g.ny * g.nx, zm * g.ny * g.nx};
+    // byte offset of coordinate x - v along each axis, indexed by v + 1
+    const uint32_t bx[3] = {xp * EB, x * EB, xm * EB};
+    const uint32_t by[3] = {yp * rowb, y * rowb, ym * rowb};
+    const uint32_t bz[3] = {zp * planexyb, z * planexyb, zm * planexyb};
+    const uint32_t nb = n * EB;
 
-    const T* __restrict__ src = static_cast<const T*>(srcv);
-    T* __restrict__ dst = static_cast<T*>(dstv);
-    const uint64_t plane = g.plane;
+    const char* __restrict__ src = static_cast<const char*>(srcv);
+    char* __restrict__ dst = static_cast<char*>(dstv);
+    const uint64_t planeb = g.plane * EB;
+    auto ld = [&](int slot, uint32_t off) -> T {
+        return *reinterpret_cast<const T*>(src + slot * planeb + off);
+    };
+    auto st = [&](int slot, uint32_t off, T v) {
+        st_pop(reinterpret_cast<T*>(dst + slot * planeb + off), v);
+    };
 
     R f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            f[i] = decode<S>(src[i * plane + (bzo[az] + byo[ay] + bx[ax])], inv_scale[i]);
+            f[i] = decode<S>(ld(i, bz[az] + by[ay] + bx[ax]), inv_scale[i]);
         } else if constexpr (SW == SW_AA_EVEN) {
-            f[i] = decode<S>(src[i * plane + n], inv_scale[i]);
+            f[i] = decode<S>(ld(i, nb), inv_scale[i]);
         } else {
-            f[i] = decode<S>(src[opp(i) * plane + (bzo[az] + byo[ay] + bx[ax])],
-                             inv_scale[opp(i)]);
+            f[i] = decode<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), inv_scale[opp(i)]);
         }
     }
 
@@ -102,31 +113,30 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     // AA odd sweep: store offsets x + v are formed after the collision, from
     // the coordinates alone, so they do not occupy registers across it (the
     // empty asm only hides the coordinates from common-subexpression reuse)
-    uint32_t fx[3] = {0, 0, 0}, fyo[3] = {0, 0, 0}, fzo[3] = {0, 0, 0};
+    uint32_t fx[3] = {0, 0, 0}, fy[3] = {0, 0, 0}, fz[3] = {0, 0, 0};
     if constexpr (SW == SW_AA_ODD) {
         uint32_t x2 = x, y2 = y, z2 = z;
         asm volatile("" : "+v"(x2), "+v"(y2), "+v"(z2));
-        const uint32_t plane_xy = g.ny * g.nx;
-        fx[0] = x2 == 0 ? g.nx - 1 : x2 - 1;
-        fx[1] = x2;
-        fx[2] = x2 + 1 == g.nx ? 0 : x2 + 1;
-        fyo[0] = (y2 == 0 ? g.ny - 1 : y2 - 1) * g.nx;
-        fyo[1] = y2 * g.nx;
-        fyo[2] = (y2 + 1 == g.ny ? 0 : y2 + 1) * g.nx;
-        fzo[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * plane_xy;
-        fzo[1] = z2 * plane_xy;
-        fzo[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * plane_xy;
+        fx[0] = (x2 == 0 ? g.nx - 1 : x2 - 1) * EB;
+        fx[1] = x2 * EB;
+        fx[2] = (x2 + 1 == g.nx ? 0 : x2 + 1) * EB;
+        fy[0] = (y2 == 0 ? g.ny - 1 : y2 - 1) * rowb;
+        fy[1] = y2 * rowb;
+        fy[2] = (y2 + 1 == g.ny ? 0 : y2 + 1) * rowb;
+        fz[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * planexyb;
+        fz[1] = z2 * planexyb;
+        fz[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * planexyb;
     }
 
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            st_pop(&dst[i * plane + n], encode<S>(f[i], scale[i]));
+            st(i, nb, encode<S>(f[i], scale[i]));
         } else if constexpr (SW == SW_AA_EVEN) {
-            st_pop(&dst[opp(i) * plane + n], encode<S>(f[i], scale[opp(i)]));
+            st(opp(i), nb, encode<S>(f[i], scale[opp(i)]));
         } else {
-            st_pop(&dst[i * plane + (fzo[az] + fyo[ay] + fx[ax])], encode<S>(f[i], scale[i]));
+            st(i, fz[az] + fy[ay] + fx[ax], encode<S>(f[i], scale[i]));
         }
     }
 }

@@ -475,6 +475,9 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
     if (nn >= 2147483648.0) return pfail(KBC_EINVAL, "box has 2^31 nodes or more");
     if (!(nu > 0.0) || !std::isfinite(nu)) return pfail(KBC_EINVAL, "nu must be finite and > 0");
     if (steps < 0) return pfail(KBC_EINVAL, "steps must be >= 0");
+    // 32-bit byte offsets inside a direction plane, as in the single-box path
+    if (nn * (double)elem_bytes_of(p->dtype) > 4294967296.0)
+        return pfail(KBC_EINVAL, "a direction plane of this box exceeds 4 GiB");
     int32_t slot = -1;
     for (size_t i = 0; i < p->slots.size(); ++i)
         if (!p->slots[i].used) {

@@ -1,11 +1,17 @@
 """Write the oracle's stored reference series (calls only oracle/ and inputs).
 
-    python tests/golden/make_oracle_golden.py
+    python tests/golden/make_oracle_golden.py [tg32|hit128]
 
-oracle_tg32_energy.txt: kinetic energy k(t) = (1/2)<|u - <u>|^2>, t = 0..100,
-of the D3Q27 KBC (s = d+t+q) run on a 32^3 periodic box, rho = 1, Taylor-Green
-start u = (U sin x cos y cos z, -U cos x sin y cos z, 0), U = 0.05,
-nu = 0.001, populations initialised at the product-form equilibrium.
+oracle_tg32_energy.txt: kinetic energy k(t) = (1/2)<|u - <u>|^2> and
+enstrophy Omega(t), t = 0..100, of the D3Q27 KBC (s = d+t+q) run on a 32^3
+periodic box, rho = 1, Taylor-Green start u = (U sin x cos y cos z,
+-U cos x sin y cos z, 0), U = 0.05, nu = 0.001, populations initialised at
+the product-form equilibrium.
+
+oracle_hit128_series.txt: k(t) and Omega(t), t = 0..steps (default 1000), of the 128^3
+decaying-turbulence run: random solenoidal start with spectrum
+~ k^4 exp(-2 (k/4)^2), u_rms = 0.04 (inputs.hit(128, 4.0, 0.04, seed=1)),
+rho = 1, nu = 5e-4, s = d+t+q.  About 10 minutes on 16 fast cores.
 """
 import os
 import sys
@@ -35,5 +41,30 @@ def tg32():
     print("wrote", path)
 
 
+def hit128(steps=1000):
+    F = oracle.init_feq(inputs.hit(128, 4.0, 0.04, seed=1))
+    path = os.path.join(HERE, "oracle_hit128_series.txt")
+    part = path + ".partial"
+    rows = []
+
+    def cb(t, F):
+        _, u = oracle.macros(F)
+        rows.append((t, oracle.energy(u), oracle.enstrophy(u)))
+        if t % 50 == 0:
+            np.savetxt(part, np.array(rows), fmt=["%d", "%.17e", "%.17e"])
+            print("t", t, flush=True)
+
+    oracle.run(F, oracle.beta_from_nu(5e-4), steps, callback=cb)
+    np.savetxt(path, np.array(rows), fmt=["%d", "%.17e", "%.17e"],
+               header="t  k(t)  Omega(t)  | 128^3 HIT k0=4 u_rms=0.04 seed=1, nu=5e-4, "
+                      f"s=d+t+q, {steps} steps, written by make_oracle_golden.py from the oracle")
+    os.remove(part)
+    print("wrote", path)
+
+
 if __name__ == "__main__":
-    tg32()
+    which = sys.argv[1] if len(sys.argv) > 1 else "tg32"
+    if which == "hit128":
+        hit128(int(sys.argv[2]) if len(sys.argv) > 2 else 1000)
+    else:
+        tg32()

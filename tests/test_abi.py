@@ -77,6 +77,9 @@ def test_options_defaults():
     ((4, 4, 4), float("nan"), kbc.F64),
     ((4, 4, 4), 1e-3, 7),
     ((2048, 1024, 1024), 1e-3, kbc.F64),
+    # a direction plane above 4 GiB (32-bit in-plane byte offsets)
+    ((1024, 1024, 1024), 1e-3, kbc.F64),
+    ((1024, 1024, 1025), 1e-3, kbc.F32_DEV),
 ])
 def test_create_rejects_bad_arguments(shape, nu, dtype):
     with pytest.raises(kbc.KbcError) as e:

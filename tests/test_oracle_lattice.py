@@ -183,3 +183,17 @@ def test_shear_wave_is_carried_by_a_uniform_flow(orc):
     c0 = np.fft.fft(u[0, 0, :, 0])[1]
     shift = -np.angle(c / c0) / (2 * np.pi / N)
     assert shift == pytest.approx(V * steps, rel=2e-3)
+
+
+def test_host_spectrum_matches_the_checker(orc):
+    """The package's host spectrum (real FFT, half spectrum) equals the
+    checker's full-FFT spectrum shell by shell."""
+    from paper_1507_02518_amd import analysis
+
+    for shape in [(16, 16, 16), (15, 12, 10), (24, 24, 24)]:
+        u = inputs.hit(shape, 3.0, 0.04, seed=2) + 0.01
+        a = analysis.spectrum(u)
+        b = orc.spectrum(u)
+        n = min(len(a), len(b))
+        assert np.allclose(a[:n], b[:n], rtol=1e-10, atol=1e-20)
+        assert abs(a.sum() - orc.energy(u)) < 1e-12 * orc.energy(u)
