@@ -20,6 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkbc_oracle.so")
 
 S_D, S_DT, S_DQ, S_DTQ = 0, 1, 2, 3
+# the same four variants in the central-moment basis (d~, d~+t~, d~+q~, d~+t~+q~)
+S_CD, S_CDT, S_CDQ, S_CDTQ = 4, 5, 6, 7
 GAMMA_ESTIMATE, GAMMA_FIXED, GAMMA_EXACT = 0, 1, 2
 DEFAULT_GAMMA_EPS = 1e-28
 
@@ -48,6 +50,11 @@ def _load():
     lib.kbco_f_from_moments.argtypes = [ctypes.c_double, _D, _D]
     lib.kbco_parts.argtypes = [ctypes.c_double, _D, _D, _D, _D, _D]
     lib.kbco_s_part.argtypes = [ctypes.c_double, _D, ctypes.c_int, _D]
+    lib.kbco_central_moments.argtypes = [_D, _D, _D]
+    lib.kbco_central_moments.restype = ctypes.c_double
+    lib.kbco_central_parts.argtypes = [ctypes.c_double, _D, _D, _D, _D, _D, _D]
+    lib.kbco_central_column.argtypes = [_D, ctypes.c_int, _D]
+    lib.kbco_s_of.argtypes = [_D, ctypes.c_int, _D]
     lib.kbco_collide.argtypes = [_D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_double, _D, _D, _D, _D]
     lib.kbco_collide.restype = ctypes.c_double
@@ -146,6 +153,39 @@ def s_part(rho: float, M, variant: int = S_DTQ) -> np.ndarray:
     M = _vec(M)
     out = np.zeros(27)
     _load().kbco_s_part(float(rho), _ptr(M), int(variant), _ptr(out))
+    return out
+
+
+def central_moments(f):
+    """Return (rho, u[3], Mt[27]) with Mt[p + 3q + 9r] = Mt_pqr."""
+    f = _vec(f)
+    Mt, u = np.zeros(27), np.zeros(3)
+    rho = _load().kbco_central_moments(_ptr(f), _ptr(Mt), _ptr(u))
+    return rho, u, Mt
+
+
+def central_parts(rho: float, u, Mt):
+    """Return (k~, d~, t~, q~) of the central-basis representation."""
+    u, Mt = _vec(u, 3), _vec(Mt)
+    k, d, t, q = (np.zeros(27) for _ in range(4))
+    _load().kbco_central_parts(float(rho), _ptr(u), _ptr(Mt), _ptr(k), _ptr(d), _ptr(t),
+                               _ptr(q))
+    return k, d, t, q
+
+
+def central_column(u, m: int) -> np.ndarray:
+    """Weight of Mt_m (m = p + 3q + 9r) in f_i / rho at velocity u."""
+    u = _vec(u, 3)
+    out = np.zeros(27)
+    _load().kbco_central_column(_ptr(u), int(m), _ptr(out))
+    return out
+
+
+def s_of(f, variant: int = S_DTQ) -> np.ndarray:
+    """Shear part of f for any variant (natural 0-3, central 4-7)."""
+    f = _vec(f)
+    out = np.zeros(27)
+    _load().kbco_s_of(_ptr(f), int(variant), _ptr(out))
     return out
 
 

@@ -263,13 +263,144 @@ void kbco_s_part(double rho, const double M[27], int variant, double s[27])
         s[i] = d[i] + (with_t ? t[i] : 0.0) + (with_q ? q[i] : 0.0);
 }
 
-/* s evaluated on an arbitrary population vector g. */
+/* ------------------------------------------------------------------------ */
+/* Central moments (section III, central basis; appendix).                  */
+/* ------------------------------------------------------------------------ */
+
+/* rho Mt_pqr = sum_i f_i (vx-ux)^p (vy-uy)^q (vz-uz)^r with u = j/rho. */
+double kbco_central_moments(const double f[27], double Mt[27], double u_out[3])
+{
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 27; ++i) {
+        int v[3];
+        kbco_velocity(i, v);
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += v[a] * f[i];
+    }
+    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q)
+            for (int p = 0; p < 3; ++p) {
+                double sum = 0.0;
+                for (int i = 0; i < 27; ++i) {
+                    int v[3];
+                    kbco_velocity(i, v);
+                    sum += f[i] * pow(v[0] - u[0], p) * pow(v[1] - u[1], q) * pow(v[2] - u[2], r);
+                }
+                Mt[p + 3 * q + 9 * r] = sum / rho;
+            }
+    if (u_out) memcpy(u_out, u, sizeof u);
+    return rho;
+}
+
+/* Inverse of the 27x27 map from populations to central moments at velocity
+ * u, C[m][i] = prod_a (v_ia - u_a)^{p_a(m)}, by Gauss-Jordan elimination with
+ * partial pivoting.  Cinv[i][m] is the weight of Mt_m in f_i / rho: the
+ * population representation in the central basis that the appendix
+ * writes out (Eqs. cmf000 to cmfxyz). */
+static void central_inverse(const double u[3], double Cinv[27][27])
+{
+    double A[27][54];
+    for (int m = 0; m < 27; ++m) {
+        const int p = m % 3, q = (m / 3) % 3, r = m / 9;
+        for (int i = 0; i < 27; ++i) {
+            int v[3];
+            kbco_velocity(i, v);
+            A[m][i] = pow(v[0] - u[0], p) * pow(v[1] - u[1], q) * pow(v[2] - u[2], r);
+        }
+        for (int k = 0; k < 27; ++k) A[m][27 + k] = (k == m) ? 1.0 : 0.0;
+    }
+    for (int c = 0; c < 27; ++c) {
+        int piv = c;
+        for (int rr = c + 1; rr < 27; ++rr)
+            if (fabs(A[rr][c]) > fabs(A[piv][c])) piv = rr;
+        if (piv != c)
+            for (int k = 0; k < 54; ++k) {
+                const double tmp = A[c][k];
+                A[c][k] = A[piv][k];
+                A[piv][k] = tmp;
+            }
+        const double d = A[c][c];
+        for (int k = 0; k < 54; ++k) A[c][k] /= d;
+        for (int rr = 0; rr < 27; ++rr) {
+            if (rr == c || A[rr][c] == 0.0) continue;
+            const double fct = A[rr][c];
+            for (int k = 0; k < 54; ++k) A[rr][k] -= fct * A[c][k];
+        }
+    }
+    /* A's right half is C^{-1}: rows indexed by the population i */
+    for (int i = 0; i < 27; ++i)
+        for (int m = 0; m < 27; ++m) Cinv[i][m] = A[i][27 + m];
+}
+
+#define CM(p, q, r) ((p) + 3 * (q) + 9 * (r))
+
+/* The parts k~, d~, t~, q~ of the central representation: each collects the
+ * terms of Eqs. cmf000-cmfxyz that carry the central moments it names.  k~
+ * holds the terms of rho and u alone; d~ those of Pi~_xy, Pi~_xz, Pi~_yz,
+ * N~_xz, N~_yz; t~ that of T~; q~ those of the seven Q~.  The normal stress
+ * differences and the trace enter through N~_xz = Mt_200 - Mt_002,
+ * N~_yz = Mt_020 - Mt_002, T~ = Mt_200 + Mt_020 + Mt_002 (section III). */
+void kbco_central_parts(double rho, const double u[3], const double Mt[27], double k[27],
+                        double d[27], double t[27], double q[27])
+{
+    double Ci[27][27];
+    central_inverse(u, Ci);
+    const double Tt = Mt[CM(2, 0, 0)] + Mt[CM(0, 2, 0)] + Mt[CM(0, 0, 2)];
+    const double Nxz = Mt[CM(2, 0, 0)] - Mt[CM(0, 0, 2)];
+    const double Nyz = Mt[CM(0, 2, 0)] - Mt[CM(0, 0, 2)];
+    for (int i = 0; i < 27; ++i) {
+        const double c200 = Ci[i][CM(2, 0, 0)], c020 = Ci[i][CM(0, 2, 0)],
+                     c002 = Ci[i][CM(0, 0, 2)];
+        /* weights of N~_xz, N~_yz and T~ once Mt_200, Mt_020, Mt_002 are
+         * written through them */
+        const double wNxz = (2.0 * c200 - c020 - c002) / 3.0;
+        const double wNyz = (-c200 + 2.0 * c020 - c002) / 3.0;
+        const double wT = (c200 + c020 + c002) / 3.0;
+        if (k)
+            k[i] = rho * (Ci[i][CM(0, 0, 0)] * Mt[CM(0, 0, 0)] + Ci[i][CM(1, 0, 0)] * Mt[CM(1, 0, 0)] +
+                          Ci[i][CM(0, 1, 0)] * Mt[CM(0, 1, 0)] + Ci[i][CM(0, 0, 1)] * Mt[CM(0, 0, 1)]);
+        if (d)
+            d[i] = rho * (Ci[i][CM(1, 1, 0)] * Mt[CM(1, 1, 0)] + Ci[i][CM(1, 0, 1)] * Mt[CM(1, 0, 1)] +
+                          Ci[i][CM(0, 1, 1)] * Mt[CM(0, 1, 1)] + wNxz * Nxz + wNyz * Nyz);
+        if (t) t[i] = rho * wT * Tt;
+        if (q)
+            q[i] = rho * (Ci[i][CM(1, 2, 0)] * Mt[CM(1, 2, 0)] + Ci[i][CM(1, 0, 2)] * Mt[CM(1, 0, 2)] +
+                          Ci[i][CM(2, 1, 0)] * Mt[CM(2, 1, 0)] + Ci[i][CM(0, 1, 2)] * Mt[CM(0, 1, 2)] +
+                          Ci[i][CM(2, 0, 1)] * Mt[CM(2, 0, 1)] + Ci[i][CM(0, 2, 1)] * Mt[CM(0, 2, 1)] +
+                          Ci[i][CM(1, 1, 1)] * Mt[CM(1, 1, 1)]);
+    }
+}
+
+/* Column of the central representation: the weight of Mt_m in f_i / rho. */
+void kbco_central_column(const double u[3], int m, double col[27])
+{
+    double Ci[27][27];
+    central_inverse(u, Ci);
+    for (int i = 0; i < 27; ++i) col[i] = Ci[i][m];
+}
+
+/* s evaluated on an arbitrary population vector g: natural-moment parts
+ * (table s_parts) for variants 0-3, central-moment parts for 4-7. */
 static void s_of(const double g[27], int variant, double s[27])
 {
+    if (variant >= KBCO_S_CD) {
+        double Mt[27], u[3], d[27], t[27], q[27];
+        const double rho = kbco_central_moments(g, Mt, u);
+        kbco_central_parts(rho, u, Mt, NULL, d, t, q);
+        const int with_t = (variant == KBCO_S_CDT || variant == KBCO_S_CDTQ);
+        const int with_q = (variant == KBCO_S_CDQ || variant == KBCO_S_CDTQ);
+        for (int i = 0; i < 27; ++i)
+            s[i] = d[i] + (with_t ? t[i] : 0.0) + (with_q ? q[i] : 0.0);
+        return;
+    }
     double M[27];
     const double rho = kbco_natural_moments(g, M);
     kbco_s_part(rho, M, variant, s);
 }
+
+/* Shear part of f for any variant (natural or central basis). */
+void kbco_s_of(const double f[27], int variant, double s[27]) { s_of(f, variant, s); }
 
 /* ------------------------------------------------------------------------ */
 /* Stabilizer: section IV, Eqs. result1 and result21.                        */

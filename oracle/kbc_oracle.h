@@ -18,7 +18,9 @@
  *   - the stored state F(t) is the pre-collision field; one step is
  *     collide (the seven-step KBC listing of section IV) followed by
  *     periodic propagation f_i(x+v_i, t+1) = f'_i(x, t) (Eq. Egeneral).
- *   - variant: 0 -> s=d, 1 -> s=d+t, 2 -> s=d+q, 3 -> s=d+t+q (section IV).
+ *   - variant: 0 -> s=d, 1 -> s=d+t, 2 -> s=d+q, 3 -> s=d+t+q (section IV,
+ *     natural moments); 4..7 -> the same four in the central-moment basis,
+ *     s = d~, d~+t~, d~+q~, d~+t~+q~ (section IV; appendix).
  *   - gamma mode: 0 -> entropic estimate gamma* (Eq. result21) with the
  *     fallback gamma=2 when <dh|dh> <= gamma_eps*rho (the paper leaves 0/0
  *     undefined); 1 -> fixed gamma = gamma_value; 2 -> exact root of the
@@ -32,7 +34,8 @@
 extern "C" {
 #endif
 
-enum { KBCO_S_D = 0, KBCO_S_DT = 1, KBCO_S_DQ = 2, KBCO_S_DTQ = 3 };
+enum { KBCO_S_D = 0, KBCO_S_DT = 1, KBCO_S_DQ = 2, KBCO_S_DTQ = 3,
+       KBCO_S_CD = 4, KBCO_S_CDT = 5, KBCO_S_CDQ = 6, KBCO_S_CDTQ = 7 };
 enum { KBCO_GAMMA_ESTIMATE = 0, KBCO_GAMMA_FIXED = 1, KBCO_GAMMA_EXACT = 2 };
 
 /* Lattice (section II, Eqs. D1Q3, D3Q27vel, weights, sound). */
@@ -57,6 +60,24 @@ void   kbco_parts(double rho, const double M[27], double k[27], double d[27],
 
 /* Shear part s for a variant (section IV): d, d+t, d+q or d+t+q. */
 void   kbco_s_part(double rho, const double M[27], int variant, double s[27]);
+
+/* Central moments rho Mt_pqr = sum_i f_i (v_ix-u_x)^p (v_iy-u_y)^q (v_iz-u_z)^r,
+ * u = j/rho (section III, central basis): Mt[p + 3q + 9r].  Returns rho;
+ * writes u to u_out unless it is NULL. */
+double kbco_central_moments(const double f[27], double Mt[27], double u_out[3]);
+
+/* Parts k~, d~, t~, q~ of the population representation in the central basis
+ * (appendix, Eqs. cmf000-cmfxyz) from rho, u and the central moments Mt.
+ * Any output may be NULL. */
+void   kbco_central_parts(double rho, const double u[3], const double Mt[27],
+                          double k[27], double d[27], double t[27], double q[27]);
+
+/* Weight of the central moment Mt_m (m = p + 3q + 9r) in f_i / rho at
+ * velocity u: one column of the inverse of the central-moment map. */
+void   kbco_central_column(const double u[3], int m, double col[27]);
+
+/* Shear part s of f for any variant 0..7. */
+void   kbco_s_of(const double f[27], int variant, double s[27]);
 
 /* One node: the seven-step collision listing of section IV.  Every output
  * pointer except P may be NULL.  Returns the gamma used. */
