@@ -60,9 +60,16 @@ extern "C" {
  * either way). */
 typedef enum { KBC_F64 = 0, KBC_F32_DEV = 1, KBC_F16_DEV = 2, KBC_F32_DEV_X = 3 } kbc_dtype;
 
-/* Shear part s of the natural-moment KBC models (section IV):
- * s = d, d+t, d+q or d+t+q.  The paper's simulations use d+t+q. */
-typedef enum { KBC_S_D = 0, KBC_S_DT = 1, KBC_S_DQ = 2, KBC_S_DTQ = 3 } kbc_variant;
+/* Shear part s of the KBC models (section IV): s = d, d+t, d+q or d+t+q
+ * built from natural moments (table s_parts), or the same four built from
+ * central moments about the node's velocity, s = d~, d~+t~, d~+q~, d~+t~+q~
+ * (the population representation in the central basis of the appendix).
+ * The paper's simulations use d+t+q.  Every variant moves the same bytes;
+ * the central ones do more arithmetic per node. */
+typedef enum {
+    KBC_S_D = 0, KBC_S_DT = 1, KBC_S_DQ = 2, KBC_S_DTQ = 3,
+    KBC_S_CD = 4, KBC_S_CDT = 5, KBC_S_CDQ = 6, KBC_S_CDTQ = 7
+} kbc_variant;
 
 /* Streaming pattern: two lattices with pull (gather) propagation, or one
  * lattice updated in place with the AA access pattern.  Results are the

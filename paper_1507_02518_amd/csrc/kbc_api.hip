@@ -193,7 +193,7 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     // byte offset
     if (nn * (double)elem_bytes(dtype) > 4294967296.0)
         return fail(KBC_EINVAL, "a direction plane of this box exceeds 4 GiB (FP64: 2^29 nodes at most)");
-    if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return fail(KBC_EINVAL, "unknown variant");
+    if (opt.variant < KBC_S_D || opt.variant > KBC_S_CDTQ) return fail(KBC_EINVAL, "unknown variant");
     if (opt.streaming != KBC_PULL && opt.streaming != KBC_AA) return fail(KBC_EINVAL, "unknown streaming");
     if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))
         return fail(KBC_EINVAL, "gamma_value must be finite");

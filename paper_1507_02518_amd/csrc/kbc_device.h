@@ -10,7 +10,21 @@
 namespace kbc {
 
 enum Storage : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_F32X = 3 };
-enum Variant : int { V_D = 0, V_DT = 1, V_DQ = 2, V_DTQ = 3 };
+// s = d, d+t, d+q, d+t+q from natural moments (table s_parts), and the same
+// four from central moments (section IV; appendix)
+enum Variant : int {
+    V_D = 0, V_DT = 1, V_DQ = 2, V_DTQ = 3,
+    V_CD = 4, V_CDT = 5, V_CDQ = 6, V_CDTQ = 7
+};
+__host__ __device__ constexpr bool is_central(int v) { return v >= V_CD; }
+__host__ __device__ constexpr bool with_t(int v)
+{
+    return v == V_DT || v == V_DTQ || v == V_CDT || v == V_CDTQ;
+}
+__host__ __device__ constexpr bool with_q(int v)
+{
+    return v == V_DQ || v == V_DTQ || v == V_CDQ || v == V_CDTQ;
+}
 enum Sweep : int { SW_PULL = 0, SW_AA_EVEN = 1, SW_AA_ODD = 2 };
 
 // D3Q27 velocities: tensor product of three copies of {-1, 0, 1}
@@ -143,7 +157,8 @@ __device__ __forceinline__ typename Traits<S>::T encode(typename Traits<S>::R v,
 //     product-form factors of section II reduce to e_0 = (4 - 2S)/3,
 //     e_{+-1} = ((2S - 1)/3 +- u)/2 per axis, f_i^eq = rho e(vx) e(vy) e(vz);
 //  3-4. ds from the differences of the 13 second- and third-order natural
-//     moments of f and f^eq (table s_parts);
+//     moments of f and f^eq (table s_parts), or, for the central variants,
+//     from the central moments of those differences (appendix);
 //  5. dh = f - f^eq - ds;
 //  6. gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, 1/f^eq_i separable;
 //     gamma = 2 where <dh|dh> <= gamma_eps * rho (0/0 at equilibrium);
@@ -188,10 +203,12 @@ __host__ __device__ __forceinline__ void moments27(const R (&g)[27], R (&M)[3][3
         }
 }
 
-// Differences of the named moments of section III between f and f^eq.
+// Differences of the named moments of section III between f and f^eq, plus
+// the three diagonal second moments (T, N_xz, N_yz are combinations of them).
 template <typename R>
 struct DMom {
     R T, Nxz, Nyz, Pxy, Pxz, Pyz, Qxyy, Qxzz, Qxxy, Qyzz, Qxxz, Qyyz, Qxyz;
+    R Dxx, Dyy, Dzz;
 };
 
 // Reciprocal and square root: IEEE-exact in FP64; in the FP32 collision the
@@ -246,15 +263,52 @@ __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
     ie[0] = e[1] * e[2] * ip;
 }
 
-// Steps 3-7 given the moment differences, f - f^eq (fneq_of(i)) and the
-// separable 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].
+// Steps 5-7 given ds_i (ds_of(i)), f - f^eq (fneq_of(i)) and the separable
+// 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].
+template <typename R, typename DsFn, typename FneqFn>
+__host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of, FneqFn fneq_of,
+                                                         const R (&iCx)[3], const R (&iA9)[9],
+                                                         double rho, const Coll& c)
+{
+    // --- 5-6. dh and the entropic scalar products --------------------------
+    R sh = R(0), hh = R(0);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const R ds = ds_of(i);
+        const R dh = fneq_of(i) - ds;
+        const R w = dh * (iCx[i % 3] * iA9[i / 3]);
+        sh += ds * w;
+        hh += dh * w;
+    }
+    R gamma;
+    if (c.gamma_fixed) {
+        gamma = R(c.gamma_value);
+    } else {
+        // ratio and fallback test in FP64 for every storage form
+        const double hhd = (double)hh, shd = (double)sh;
+        gamma = (hhd <= c.gamma_eps * rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
+    }
+
+    // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
+    // dh = (f - f^eq) - ds as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
+    const R c1 = R(c.beta) * (R(2) - gamma);
+    const R c2 = R(c.beta) * gamma;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const R ds = ds_of(i);
+        const R fneq = fneq_of(i);
+        f[i] = f[i] - c1 * ds - c2 * fneq;
+    }
+}
+
+// Steps 3-7 for the natural-moment variants: ds_i from table s_parts.
 template <typename R, int V, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d, FneqFn fneq_of,
                                                    const R (&iCx)[3], const R (&iA9)[9],
                                                    double rho, const Coll& c)
 {
-    constexpr bool WT = (V == V_DT || V == V_DTQ);
-    constexpr bool WQ = (V == V_DQ || V == V_DTQ);
+    constexpr bool WT = with_t(V);
+    constexpr bool WQ = with_q(V);
     // table s_parts: value of ds per direction class
     const R t6 = WT ? d.T * R(1.0 / 6.0) : R(0);
     const R sRest = WT ? -d.T : R(0);
@@ -286,36 +340,101 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
         }
         return R(sx * sy * sz) * qC;
     };
+    kbc_gamma_relax<R>(f, ds_of, fneq_of, iCx, iA9, rho, c);
+}
 
-    // --- 5-6. dh and the entropic scalar products --------------------------
-    R sh = R(0), hh = R(0);
+// Steps 3-7 for the central-moment variants (section IV; appendix).  The
+// shear part is rebuilt from central moments of f - f^eq about the node's u.
+// Because f - f^eq carries no mass and no momentum, its second-order central
+// moments equal the natural ones, and a third-order one is the natural one
+// minus u times second-order ones, e.g. dMt_120 = dM_120 - 2u_y dM_110 -
+// u_x dM_020 (raw moments throughout).  The population representation in
+// the central basis is the tensor product of one-dimensional inverses: on an
+// axis with velocity u the central moments (m0, m1, m2) give
+//   f_{-1} = (u^2 - u)/2 m0 + (u - 1/2) m1 + m2/2,
+//   f_0    = (1 - u^2) m0 - 2u m1 - m2,
+//   f_{+1} = (u^2 + u)/2 m0 + (u + 1/2) m1 + m2/2,
+// so ds~ is three separable passes over a 3x3x3 array that holds only the
+// 13 second- and third-order entries kept in s.
+template <typename R, int V, typename FneqFn>
+__host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMom<R>& d,
+                                                           const R (&u)[3], FneqFn fneq_of,
+                                                           const R (&iCx)[3], const R (&iA9)[9],
+                                                           double rho, const Coll& c)
+{
+    constexpr bool WT = with_t(V);
+    constexpr bool WQ = with_q(V);
+    R X[3][3][3];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R ds = ds_of(i);
-        const R dh = fneq_of(i) - ds;
-        const R w = dh * (iCx[i % 3] * iA9[i / 3]);
-        sh += ds * w;
-        hh += dh * w;
-    }
-    R gamma;
-    if (c.gamma_fixed) {
-        gamma = R(c.gamma_value);
+    for (int k = 0; k < 27; ++k) X[k % 3][(k / 3) % 3][k / 9] = R(0);
+    if constexpr (WT) {
+        X[2][0][0] = d.Dxx;
+        X[0][2][0] = d.Dyy;
+        X[0][0][2] = d.Dzz;
     } else {
-        // ratio and fallback test in FP64 for every storage form
-        const double hhd = (double)hh, shd = (double)sh;
-        gamma = (hhd <= c.gamma_eps * rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
+        // d~ alone: the deviatoric (trace-free) part of the diagonal
+        const R t3 = (d.Dxx + d.Dyy + d.Dzz) * R(1.0 / 3.0);
+        X[2][0][0] = d.Dxx - t3;
+        X[0][2][0] = d.Dyy - t3;
+        X[0][0][2] = d.Dzz - t3;
     }
-
-    // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
-    // dh = (f - f^eq) - ds as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
-    const R c1 = R(c.beta) * (R(2) - gamma);
-    const R c2 = R(c.beta) * gamma;
+    X[1][1][0] = d.Pxy;
+    X[1][0][1] = d.Pxz;
+    X[0][1][1] = d.Pyz;
+    if constexpr (WQ) {
+        const R ux = u[0], uy = u[1], uz = u[2];
+        X[1][2][0] = d.Qxyy - R(2) * uy * d.Pxy - ux * d.Dyy;
+        X[1][0][2] = d.Qxzz - R(2) * uz * d.Pxz - ux * d.Dzz;
+        X[2][1][0] = d.Qxxy - R(2) * ux * d.Pxy - uy * d.Dxx;
+        X[0][1][2] = d.Qyzz - R(2) * uz * d.Pyz - uy * d.Dzz;
+        X[2][0][1] = d.Qxxz - R(2) * ux * d.Pxz - uz * d.Dxx;
+        X[0][2][1] = d.Qyyz - R(2) * uy * d.Pyz - uz * d.Dyy;
+        X[1][1][1] = d.Qxyz - ux * d.Pyz - uy * d.Pxz - uz * d.Pxy;
+    }
+    // G[a][v+1][p]: weight of the central moment of order p on axis a in the
+    // population with velocity v
+    R G[3][3][3];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R ds = ds_of(i);
-        const R fneq = fneq_of(i);
-        f[i] = f[i] - c1 * ds - c2 * fneq;
+    for (int a = 0; a < 3; ++a) {
+        const R ua = u[a], u2 = ua * ua;
+        G[a][0][0] = R(0.5) * (u2 - ua);
+        G[a][0][1] = ua - R(0.5);
+        G[a][0][2] = R(0.5);
+        G[a][1][0] = R(1) - u2;
+        G[a][1][1] = R(-2) * ua;
+        G[a][1][2] = R(-1);
+        G[a][2][0] = R(0.5) * (u2 + ua);
+        G[a][2][1] = ua + R(0.5);
+        G[a][2][2] = R(0.5);
     }
+    // z, then y, then x
+    R Z1[3][3][3], Z2[3][3][3], ds[27];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int vz = 0; vz < 3; ++vz)
+                Z1[p][q][vz] = G[2][vz][0] * X[p][q][0] + G[2][vz][1] * X[p][q][1] +
+                               G[2][vz][2] * X[p][q][2];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int vy = 0; vy < 3; ++vy)
+#pragma unroll
+            for (int vz = 0; vz < 3; ++vz)
+                Z2[p][vy][vz] = G[1][vy][0] * Z1[p][0][vz] + G[1][vy][1] * Z1[p][1][vz] +
+                                G[1][vy][2] * Z1[p][2][vz];
+#pragma unroll
+    for (int vx = 0; vx < 3; ++vx)
+#pragma unroll
+        for (int vy = 0; vy < 3; ++vy)
+#pragma unroll
+            for (int vz = 0; vz < 3; ++vz)
+                ds[vx + 3 * vy + 9 * vz] = G[0][vx][0] * Z2[0][vy][vz] +
+                                           G[0][vx][1] * Z2[1][vy][vz] +
+                                           G[0][vx][2] * Z2[2][vy][vz];
+    kbc_gamma_relax<R>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c);
 }
 
 template <int S, int V>
@@ -380,6 +499,9 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         d.Qxxz = M[2][0][1];
         d.Qyyz = M[0][2][1];
         d.Qxyz = M[1][1][1];
+        d.Dxx = M[2][0][0];
+        d.Dyy = M[0][2][0];
+        d.Dzz = M[0][0][2];
         R iE[3][3], Ef[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -392,7 +514,13 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         for (int yz = 0; yz < 9; ++yz) iA9[yz] = iE[1][yz % 3] * iE[2][yz / 3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) iCx[ax] = (R)irho * iE[0][ax];
-        kbc_relax<R, V>(f, d, [&](int i) -> R { return fneq[i]; }, iCx, iA9, rho, c);
+        auto fneq_of = [&](int i) -> R { return fneq[i]; };
+        if constexpr (is_central(V)) {
+            const R uf[3] = {(R)u[0], (R)u[1], (R)u[2]};
+            kbc_relax_central<R, V>(f, d, uf, fneq_of, iCx, iA9, rho, c);
+        } else {
+            kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, rho, c);
+        }
     } else {
         // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ----
         R M[3][3][3];
@@ -436,6 +564,9 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         d.Qxxz = M[2][0][1] - rho * m2[0] * u[2];
         d.Qyyz = M[0][2][1] - rho * m2[1] * u[2];
         d.Qxyz = M[1][1][1] - rho * u[0] * u[1] * u[2];
+        d.Dxx = dD[0];
+        d.Dyy = dD[1];
+        d.Dzz = dD[2];
 
         // equilibrium (or its deviation from W) and 1/f^eq, from the marginals
         R A9[9], B9[9], iA9[9];
@@ -460,7 +591,8 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             if constexpr (DEV) return f[i] - (A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
             else return f[i] - A9[yz] * Cx[ax];
         };
-        kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, (double)rho, c);
+        if constexpr (is_central(V)) kbc_relax_central<R, V>(f, d, u, fneq_of, iCx, iA9, (double)rho, c);
+        else kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, (double)rho, c);
     }
 }
 

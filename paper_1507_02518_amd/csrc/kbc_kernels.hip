@@ -223,6 +223,10 @@ PoolFn pool_fn_v(int v, int sw)
     case V_D: return pool_fn_sw<S, V_D>(sw);
     case V_DT: return pool_fn_sw<S, V_DT>(sw);
     case V_DQ: return pool_fn_sw<S, V_DQ>(sw);
+    case V_CD: return pool_fn_sw<S, V_CD>(sw);
+    case V_CDT: return pool_fn_sw<S, V_CDT>(sw);
+    case V_CDQ: return pool_fn_sw<S, V_CDQ>(sw);
+    case V_CDTQ: return pool_fn_sw<S, V_CDTQ>(sw);
     default: return pool_fn_sw<S, V_DTQ>(sw);
     }
 }
@@ -243,6 +247,10 @@ StepFn step_fn_v(int v, int sw)
     case V_D: return step_fn<S, V_D>(sw);
     case V_DT: return step_fn<S, V_DT>(sw);
     case V_DQ: return step_fn<S, V_DQ>(sw);
+    case V_CD: return step_fn<S, V_CD>(sw);
+    case V_CDT: return step_fn<S, V_CDT>(sw);
+    case V_CDQ: return step_fn<S, V_CDQ>(sw);
+    case V_CDTQ: return step_fn<S, V_CDTQ>(sw);
     default: return step_fn<S, V_DTQ>(sw);
     }
 }

@@ -353,7 +353,7 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
     else kbc_options_default(&opt);
     if (dtype != KBC_F64 && dtype != KBC_F32_DEV && dtype != KBC_F16_DEV && dtype != KBC_F32_DEV_X)
         return pfail(KBC_EINVAL, "unknown dtype");
-    if (opt.variant < KBC_S_D || opt.variant > KBC_S_DTQ) return pfail(KBC_EINVAL, "unknown variant");
+    if (opt.variant < KBC_S_D || opt.variant > KBC_S_CDTQ) return pfail(KBC_EINVAL, "unknown variant");
     if (max_slots < 1 || max_slots > 65536) return pfail(KBC_EINVAL, "max_slots must be in [1, 65536]");
     if (hbm_budget_bytes < Arena::kGrain) return pfail(KBC_EINVAL, "budget below 64 KiB");
     if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))

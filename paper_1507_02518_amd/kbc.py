@@ -27,6 +27,7 @@ KBC_ESTATE = -6
 
 F64, F32_DEV, F16_DEV, F32_DEV_X = 0, 1, 2, 3
 S_D, S_DT, S_DQ, S_DTQ = 0, 1, 2, 3
+S_CD, S_CDT, S_CDQ, S_CDTQ = 4, 5, 6, 7   # central-moment variants
 PULL, AA = 0, 1
 
 DTYPES = {"f64": F64, "f32": F32_DEV, "f16": F16_DEV, "f32x": F32_DEV_X}

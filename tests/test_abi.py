@@ -134,3 +134,23 @@ def test_pool_create_rejects_bad_arguments():
     lib = kbc.load()
     assert lib.kbc_pool_destroy(None) == kbc.KBC_OK
     assert lib.kbc_pool_advance(None, 1) == kbc.KBC_EINVAL
+
+
+def test_device_collision_built_for_the_host_matches_the_oracle(orc):
+    """kbc::collide (the kernels' per-node update, compiled here for the CPU)
+    against the oracle's collision for all eight variants, natural and
+    central: FP64 within 5e-15, FP32 deviation storage with FP64-formed
+    non-equilibrium within 3e-8 (measured 1.7e-15 and 7e-9)."""
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("ROCm clang++ not present")
+    odir = os.path.join(ROOT, "oracle")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "cc")
+        subprocess.run([clang, "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__",
+                        "-I/opt/rocm/include", "-I", CSRC, "-I", odir,
+                        os.path.join(ROOT, "tests", "host", "collide_check.cpp"),
+                        "-L", odir, "-lkbc_oracle", f"-Wl,-rpath,{odir}", "-o", exe],
+                       check=True, capture_output=True)
+        r = subprocess.run([exe, "5e-15", "3e-8"], capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr

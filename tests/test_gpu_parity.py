@@ -25,6 +25,18 @@ def _oracle_run(orc, u, nu, steps, rho=None, **kw):
     return orc.run(orc.init_feq(u, rho), orc.beta_from_nu(nu), steps, **kw)
 
 
+_ORACLE_CACHE = {}
+
+
+def _oracle_cached(orc, u, nu, steps, variant):
+    """Oracle run of the 32^3 Taylor-Green case, shared by tests that use the
+    same start, viscosity, step count and variant."""
+    key = (u.shape, float(np.abs(u).max()), nu, steps, variant)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = _oracle_run(orc, u, nu, steps, variant=variant)
+    return _ORACLE_CACHE[key]
+
+
 def _box(shape, nu, dtype=kbc.F64, **kw):
     return kbc.Box(shape, nu, dtype, **kw)
 
@@ -56,6 +68,25 @@ def test_taylor_green_32_fp64_energy_series_and_populations(orc, streaming):
     assert rel_k <= 1e-12 and rel_o <= 1e-12
 
 
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+def test_taylor_green_32_central_kbc_populations(orc, streaming):
+    """The central-moment default s = d~+t~+q~ on the 32^3 Taylor-Green case
+    (U = 0.05, nu = 0.001), 100 steps: populations element-wise and k(100)
+    against the oracle."""
+    u0 = inputs.taylor_green(32, 0.05)
+    with _box(32, 1e-3, variant=kbc.S_CDTQ, streaming=streaming) as b:
+        b.init_velocity(u0)
+        b.step(100)
+        f = b.populations()
+        k = b.energy()
+    F = _oracle_run(orc, u0, 1e-3, 100, variant=kbc.S_CDTQ)
+    _, uo = orc.macros(F)
+    err = np.abs(f - F).max()
+    rel_k = abs(k / orc.energy(uo) - 1)
+    say(f"TG32 central streaming={streaming}: max|df|={err:.3e} rel dk={rel_k:.3e}")
+    assert err <= TOL_F64 and rel_k <= 1e-12
+
+
 # --------------------------------------------------- ragged / variants ----
 
 RAGGED = [(13, 7, 5), (1, 9, 4), (33, 17, 3), (2, 2, 2), (1, 1, 1), (70, 3, 2)]
@@ -67,7 +98,7 @@ def test_ragged_boxes_all_variants(orc, shape, streaming):
     u = inputs.smooth_random(shape, 0.06, seed=sum(shape))
     rho = inputs.random_density(shape, 0.02, seed=sum(shape))
     nu = 3e-4
-    for variant in (0, 1, 2, 3):
+    for variant in range(8):
         for steps in (6, 7):
             F = _oracle_run(orc, u, nu, steps, rho, variant=variant)
             with _box(shape, nu, variant=variant, streaming=streaming) as b:
@@ -79,13 +110,13 @@ def test_ragged_boxes_all_variants(orc, shape, streaming):
     say(f"ragged {shape} streaming={streaming}: ok")
 
 
-@pytest.mark.parametrize("gamma_kind", ["lbgk", "rlb"])
+@pytest.mark.parametrize("gamma_kind", ["lbgk", "rlb", "rlb_central"])
 def test_forced_gamma_paths(orc, gamma_kind):
     shape = (12, 10, 8)
     nu = 2e-3
     beta = orc.beta_from_nu(nu)
     g = 2.0 if gamma_kind == "lbgk" else 1.0 / beta
-    variant = 3 if gamma_kind == "lbgk" else 1
+    variant = {"lbgk": 3, "rlb": 1, "rlb_central": 5}[gamma_kind]
     u = inputs.smooth_random(shape, 0.05, seed=3)
     F = _oracle_run(orc, u, nu, 9, variant=variant, gamma=g)
     with _box(shape, nu, variant=variant, gamma=g) as b:
@@ -249,6 +280,30 @@ def test_full_size_fp64_sampled_against_oracle(orc, n, streaming):
     assert err <= 1e-14
 
 
+def test_full_size_central_kbc_sampled_against_oracle(orc):
+    """256^3 decaying-turbulence start with s = d~+t~+q~ (pull, the timed
+    launch shape): two GPU steps, 32 sampled nodes against the oracle."""
+    n = 256
+    u = inputs.hit(n, 4.0, 0.04, seed=1)
+    rng = np.random.default_rng(7)
+    nodes = rng.integers(0, n ** 3, size=32)
+    nodes[:2] = [0, n ** 3 - 1]
+    with _box(n, 5e-4, variant=kbc.S_CDTQ) as b:
+        b.init_velocity(u)
+        b.step(2)
+        got = b.sample(nodes)
+    nx = ny = nz = n
+    ref = []
+    for node in nodes:
+        x, y, z = node % nx, (node // nx) % ny, node // (nx * ny)
+        ix, iy, iz = (np.arange(c - 2, c + 3) % m for c, m in ((x, nx), (y, ny), (z, nz)))
+        ub = np.ascontiguousarray(u[:, iz][:, :, iy][:, :, :, ix])
+        ref.append(_oracle_run(orc, ub, 5e-4, 2, variant=kbc.S_CDTQ)[:, 2, 2, 2])
+    err = np.abs(got - np.array(ref)).max()
+    say(f"full size 256^3 central: sampled max|df|={err:.3e}")
+    assert err <= 1e-14
+
+
 def test_full_size_conservation_512_fp32_aa():
     """512^3 in-place AA with FP32 deviation storage: total mass and momentum
     are conserved to the storage precision over 10 steps."""
@@ -276,20 +331,23 @@ def test_full_size_conservation_512_fp32_aa():
                                                (kbc.F32_DEV_X, 1e-7, 1e-8),
                                                (kbc.F16_DEV, 1.5e-4, 6e-5)])
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
-def test_deviation_storage_error_against_oracle(orc, dtype, tol_k, tol_f, streaming):
+@pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
+def test_deviation_storage_error_against_oracle(orc, dtype, tol_k, tol_f, streaming, variant):
     """FP32 / FP16 deviation storage on the 32^3 Taylor-Green case: relative
-    energy error and max population error after 100 steps (stated bounds)."""
+    energy error and max population error after 100 steps (stated bounds),
+    natural and central default variants."""
     u0 = inputs.taylor_green(32, 0.05)
-    F = _oracle_run(orc, u0, 1e-3, 100)
+    F = _oracle_cached(orc, u0, 1e-3, 100, variant)
     _, uo = orc.macros(F)
-    with _box(32, 1e-3, dtype, streaming=streaming) as b:
+    with _box(32, 1e-3, dtype, streaming=streaming, variant=variant) as b:
         b.init_velocity(u0)
         b.step(100)
         f = b.populations()
         k = b.energy()
     ek = abs(k / orc.energy(uo) - 1)
     ef = np.abs(f - F).max()
-    say(f"dtype={dtype} streaming={streaming}: rel energy error {ek:.3e}, max|df| {ef:.3e}")
+    say(f"dtype={dtype} streaming={streaming} variant={variant}: rel energy error {ek:.3e}, "
+        f"max|df| {ef:.3e}")
     assert ek <= tol_k and ef <= tol_f
 
 

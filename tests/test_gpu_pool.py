@@ -34,8 +34,9 @@ BOXES = [((13, 9, 7), 3e-4, 7), ((16, 16, 16), 1e-3, 12), ((20, 6, 11), 5e-3, 9)
          ((8, 8, 8), 2e-4, 1)]
 
 
-def test_pool_boxes_match_oracle(orc):
-    with kbc.Pool(64 << 20, kbc.F64, max_slots=8) as pool:
+@pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
+def test_pool_boxes_match_oracle(orc, variant):
+    with kbc.Pool(64 << 20, kbc.F64, variant=variant, max_slots=8) as pool:
         slots = []
         for i, (shape, nu, steps) in enumerate(BOXES):
             u = inputs.smooth_random(shape, 0.05, seed=i)
@@ -44,12 +45,12 @@ def test_pool_boxes_match_oracle(orc):
             pool.advance(3)
         for slot, shape, nu, steps, u in slots:
             k, w, rho, ug = pool.result(slot, shape)
-            F = orc.run(orc.init_feq(u), orc.beta_from_nu(nu), steps)
+            F = orc.run(orc.init_feq(u), orc.beta_from_nu(nu), steps, variant=variant)
             rho_o, u_o = orc.macros(F)
             assert np.abs(rho - rho_o).max() <= 1e-14
             assert np.abs(ug - u_o).max() <= 1e-14
             assert k == pytest.approx(orc.energy(u_o), rel=1e-12)
-    say("pool vs oracle ok")
+    say(f"pool vs oracle ok (variant {variant})")
 
 
 @pytest.mark.parametrize("dtype", [kbc.F64, kbc.F32_DEV_X, kbc.F16_DEV])
