@@ -198,3 +198,19 @@ def test_host_spectrum_matches_the_checker(orc):
         n = min(len(a), len(b))
         assert np.allclose(a[:n], b[:n], rtol=1e-10, atol=1e-20)
         assert abs(a.sum() - orc.energy(u)) < 1e-12 * orc.energy(u)
+
+
+def test_kida_start_is_solenoidal_and_symmetric():
+    """Eq. kida: the velocity is divergence-free (spectral derivative) and
+    invariant under the cyclic relabelling x -> y -> z -> x of coordinates and
+    components, u_y(x, y, z) = u_x(y, z, x); arrays are [z][y][x]."""
+    n = 24
+    u = inputs.kida(n, 0.05)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    div = 1j * (kx * np.fft.fftn(u[0]) + ky * np.fft.fftn(u[1]) + kz * np.fft.fftn(u[2]))
+    assert np.abs(np.fft.ifftn(div)).max() < 1e-14
+    # (T A)[z, y, x] = A[x, z, y] is A evaluated at (x, y, z) -> (y, z, x)
+    assert np.abs(u[1] - np.transpose(u[0], (1, 2, 0))).max() < 1e-16
+    assert np.abs(u[2] - np.transpose(u[1], (1, 2, 0))).max() < 1e-16
+    assert np.abs(u[0] - np.transpose(u[2], (1, 2, 0))).max() < 1e-16
