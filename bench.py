@@ -8,8 +8,9 @@ u_rms = 0.04, rho = 1, nu = 5e-4, populations at the product-form
 equilibrium; KBC model s = d+t+q with the entropic stabilizer.  One step is
 one launch of the fused kernel over all 16.8 M nodes.  The headline line is
 FP64 storage with pull streaming (the form matched element-wise to the CPU
-oracle); the other storage forms, the s = d variant and the central-moment
-default s = d~+t~+q~ are measured on the same field and listed under "forms".
+oracle); the other storage forms, the s = d variant, the central-moment
+default s = d~+t~+q~ and the exact stabilizer (root of the entropy condition
+at every node) are measured on the same field and listed under "forms".
 
 Prints one JSON line with MLUPS, the roofline of the step kernel (HBM bound,
 algorithmic bytes 2 * 27 * bytes-per-population per node and step, timed with
@@ -74,11 +75,12 @@ def read_counters():
         return None
 
 
-def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, variant=None):
+def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, variant=None,
+              gamma=None):
     # the box enqueues on `stream` (a torch stream of default priority); the
     # events are recorded on the same stream, so they bracket the launches
     variant = kbc.S_DTQ if variant is None else variant
-    with kbc.Box(N, NU, dtype, variant=variant, streaming=streaming,
+    with kbc.Box(N, NU, dtype, variant=variant, streaming=streaming, gamma=gamma,
                  stream=stream.cuda_stream) as box:
         kbc.kbc_init_velocity_device(box.h, u_dev.data_ptr(), None)
         box.step(warmup)
@@ -320,9 +322,15 @@ def main():
                                   ("f64_pull_s_d", kbc.F64, kbc.PULL, kbc.S_D),
                                   ("f64_pull_central", kbc.F64, kbc.PULL, C),
                                   ("f32devx_pull_central", kbc.F32_DEV_X, kbc.PULL, C),
-                                  ("f16dev_aa_central", kbc.F16_DEV, kbc.AA, C)]:
+                                  ("f16dev_aa_central", kbc.F16_DEV, kbc.AA, C),
+                                  ("f64_pull_exact_gamma", kbc.F64, kbc.PULL, "exact"),
+                                  ("f32devx_pull_exact_gamma", kbc.F32_DEV_X, kbc.PULL,
+                                   "exact")]:
             log(f"[bench] {name}")
-            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup, stream, var)
+            gamma = None
+            if var == "exact":
+                var, gamma = None, "exact"
+            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup, stream, var, gamma)
             forms[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
             log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
     log("[bench] copy ceiling")

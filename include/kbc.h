@@ -76,12 +76,23 @@ typedef enum {
  * same; AA halves the memory footprint. */
 typedef enum { KBC_PULL = 0, KBC_AA = 1 } kbc_streaming;
 
+/* Stabilizer gamma (section IV).  KBC_GAMMA_ENTROPIC: the estimate gamma*
+ * of Eq. result21 (the paper's scheme).  KBC_GAMMA_FIXED: gamma =
+ * gamma_value everywhere (2 = LBGK, 1/beta = regularised LB).
+ * KBC_GAMMA_EXACT: the root of the entropy-maximum condition Eq. result1 at
+ * every node, found by safeguarded Newton iteration from gamma* in FP64
+ * (about 3-6 iterations of 27 logarithms per node: an ALU-bound kernel);
+ * gamma = 2 where <dh|dh> <= gamma_eps rho or where the condition has no
+ * root with all post-collision populations positive.  Single boxes only;
+ * kbc_pool_create rejects it. */
+typedef enum { KBC_GAMMA_ENTROPIC = 0, KBC_GAMMA_FIXED = 1, KBC_GAMMA_EXACT = 2 } kbc_gamma_mode;
+
 typedef struct kbc_options {
     int32_t variant;        /* kbc_variant; default KBC_S_DTQ */
     int32_t streaming;      /* kbc_streaming; default KBC_PULL */
-    int32_t gamma_fixed;    /* 0: entropic gamma; 1: gamma = gamma_value */
+    int32_t gamma_mode;     /* kbc_gamma_mode; default KBC_GAMMA_ENTROPIC */
     int32_t device;         /* HIP device ordinal; -1 = current device */
-    double gamma_value;     /* used when gamma_fixed = 1 (2 = LBGK, 1/beta = RLB) */
+    double gamma_value;     /* used with KBC_GAMMA_FIXED (2 = LBGK, 1/beta = RLB) */
     double gamma_eps;       /* gamma = 2 where <dh|dh> <= gamma_eps * rho;
                                <= 0 selects the default (1e-28 for FP64,
                                1e-16 for the FP32 collision) */

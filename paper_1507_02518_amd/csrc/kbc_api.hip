@@ -62,6 +62,7 @@ struct kbc_box {
     int64_t shape[3];
     Geom g;
     int dtype, variant, streaming;
+    bool exact_gamma;   // root of Eq. result1 instead of the estimate
     Coll coll;
     double nu;
     int device;
@@ -164,7 +165,7 @@ void kbc_options_default(kbc_options* opt)
     std::memset(opt, 0, sizeof(*opt));
     opt->variant = KBC_S_DTQ;
     opt->streaming = KBC_PULL;
-    opt->gamma_fixed = 0;
+    opt->gamma_mode = KBC_GAMMA_ENTROPIC;
     opt->device = -1;
     opt->gamma_value = 2.0;
     opt->gamma_eps = 0.0;
@@ -195,7 +196,9 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
         return fail(KBC_EINVAL, "a direction plane of this box exceeds 4 GiB (FP64: 2^29 nodes at most)");
     if (opt.variant < KBC_S_D || opt.variant > KBC_S_CDTQ) return fail(KBC_EINVAL, "unknown variant");
     if (opt.streaming != KBC_PULL && opt.streaming != KBC_AA) return fail(KBC_EINVAL, "unknown streaming");
-    if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))
+    if (opt.gamma_mode < KBC_GAMMA_ENTROPIC || opt.gamma_mode > KBC_GAMMA_EXACT)
+        return fail(KBC_EINVAL, "unknown gamma_mode");
+    if (opt.gamma_mode == KBC_GAMMA_FIXED && !std::isfinite(opt.gamma_value))
         return fail(KBC_EINVAL, "gamma_value must be finite");
 
     kbc_box* h = new (std::nothrow) kbc_box();
@@ -221,7 +224,8 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     h->coll.inv_beta = 1.0 / beta;
     h->coll.c2 = 2.0 - 1.0 / beta;
     h->coll.gamma_eps = opt.gamma_eps > 0.0 ? opt.gamma_eps : (dtype == KBC_F64 ? 1e-28 : 1e-16);
-    h->coll.gamma_fixed = opt.gamma_fixed ? 1 : 0;
+    h->coll.gamma_fixed = opt.gamma_mode == KBC_GAMMA_FIXED ? 1 : 0;
+    h->exact_gamma = opt.gamma_mode == KBC_GAMMA_EXACT;
     h->coll.gamma_value = opt.gamma_value;
     for (int i = 0; i < 27; ++i) h->scale[i] = h->inv_scale[i] = 1.0f;
 
@@ -351,7 +355,7 @@ int kbc_step(kbc_handle h, int64_t n)
             p.src = h->buf[0];
             p.dst = h->buf[0];
         }
-        KBC_HIP(launch_step(h->dtype, h->variant, sweep, p, h->stream));
+        KBC_HIP(launch_step(h->dtype, h->variant, sweep, h->exact_gamma, p, h->stream));
         if (h->streaming == KBC_PULL) h->cur = 1 - h->cur;
         h->t += 1;
     }

@@ -263,9 +263,69 @@ __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
     ie[0] = e[1] * e[2] * ip;
 }
 
+// Exact stabilizer (section IV, Eq. result1): the root in gamma of
+//   G(gamma) = sum_i dh_i ln(1 + ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / f^eq_i),
+// whose logarithm arguments are f'_i / f^eq_i.  On the interval where all of
+// them are positive G falls strictly (G' = -beta sum_i dh_i^2 / (f^eq_i arg_i)),
+// so the root there is unique.  Newton's method from the estimate g0, each
+// iterate kept inside a bracket that shrinks with the sign of G (a step that
+// leaves it is replaced by bisection); FP64 for every storage form.  A change
+// dg of gamma moves f'_i by beta dg dh_i, so the iteration stops once the
+// last correction moves no population by more than 1e-16 f^eq_i: further
+// digits of gamma cannot change the result, and where dh << ds they are not
+// determined by G to begin with.  Returns false, leaving gamma to the
+// caller, when no bracket exists.
+template <typename DsFn, typename FneqFn, typename IfeqFn>
+__host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, IfeqFn ifeq_of,
+                                                 double beta, double g0, double& gamma)
+{
+    const double a = 2.0 * beta - 1.0;
+    const double inf = __builtin_inf();
+    double lo = -inf, hi = inf, hmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const double ds = (double)ds_of(i), dh = (double)fneq_of(i) - ds;
+        const double w = (double)ifeq_of(i);
+        hmax = fmax(hmax, fabs(dh * w));
+        if (dh != 0.0) {
+            // arg_i > 0  <=>  beta gamma dh_i w < 1 + (dh_i - a ds_i) w
+            const double b = (1.0 + (dh - a * ds) * w) / (beta * dh * w);
+            if (dh > 0.0) hi = fmin(hi, b);
+            else lo = fmax(lo, b);
+        }
+    }
+    if (!(lo < hi) || !(lo > -inf) || !(hi < inf)) return false;
+    double g = (g0 > lo && g0 < hi) ? g0 : 0.5 * (lo + hi);
+    const double dg_tol = 1e-16 / (beta * hmax);
+    for (int it = 0; it < 80; ++it) {
+        double G = 0.0, D = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const double ds = (double)ds_of(i), dh = (double)fneq_of(i) - ds;
+            const double w = (double)ifeq_of(i);
+            const double x = ((1.0 - beta * g) * dh - a * ds) * w;
+            G += dh * log1p(x);
+            D += dh * dh * w / (1.0 + x);
+        }
+        const double step = G / (beta * D);      // Newton step, G' = -beta D
+        if (fabs(step) <= dg_tol) {              // converged (also when the step
+            g += step;                           // is below one ulp of g)
+            break;
+        }
+        if (G > 0.0) lo = g;
+        else hi = g;
+        double gn = g + step;
+        if (!(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+        g = gn;
+    }
+    gamma = g;
+    return true;
+}
+
 // Steps 5-7 given ds_i (ds_of(i)), f - f^eq (fneq_of(i)) and the separable
-// 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].
-template <typename R, typename DsFn, typename FneqFn>
+// 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].  GX selects the exact
+// stabilizer (root of Eq. result1) in place of the estimate gamma*.
+template <typename R, bool GX, typename DsFn, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of, FneqFn fneq_of,
                                                          const R (&iCx)[3], const R (&iA9)[9],
                                                          double rho, const Coll& c)
@@ -286,7 +346,20 @@ __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of,
     } else {
         // ratio and fallback test in FP64 for every storage form
         const double hhd = (double)hh, shd = (double)sh;
-        gamma = (hhd <= c.gamma_eps * rho) ? R(2) : R(c.inv_beta - c.c2 * shd / hhd);
+        if (hhd <= c.gamma_eps * rho) {
+            gamma = R(2);
+        } else {
+            double g = c.inv_beta - c.c2 * shd / hhd;
+            if constexpr (GX) {
+                double ge;
+                g = gamma_exact_root(ds_of, fneq_of,
+                                     [&](int i) -> R { return iCx[i % 3] * iA9[i / 3]; },
+                                     c.beta, g, ge)
+                        ? ge
+                        : 2.0;
+            }
+            gamma = R(g);
+        }
     }
 
     // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
@@ -302,7 +375,7 @@ __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of,
 }
 
 // Steps 3-7 for the natural-moment variants: ds_i from table s_parts.
-template <typename R, int V, typename FneqFn>
+template <typename R, int V, bool GX, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d, FneqFn fneq_of,
                                                    const R (&iCx)[3], const R (&iA9)[9],
                                                    double rho, const Coll& c)
@@ -340,7 +413,7 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
         }
         return R(sx * sy * sz) * qC;
     };
-    kbc_gamma_relax<R>(f, ds_of, fneq_of, iCx, iA9, rho, c);
+    kbc_gamma_relax<R, GX>(f, ds_of, fneq_of, iCx, iA9, rho, c);
 }
 
 // Steps 3-7 for the central-moment variants (section IV; appendix).  The
@@ -356,7 +429,7 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
 //   f_{+1} = (u^2 + u)/2 m0 + (u + 1/2) m1 + m2/2,
 // so ds~ is three separable passes over a 3x3x3 array that holds only the
 // 13 second- and third-order entries kept in s.
-template <typename R, int V, typename FneqFn>
+template <typename R, int V, bool GX, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMom<R>& d,
                                                            const R (&u)[3], FneqFn fneq_of,
                                                            const R (&iCx)[3], const R (&iA9)[9],
@@ -434,10 +507,10 @@ __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMo
                 ds[vx + 3 * vy + 9 * vz] = G[0][vx][0] * Z2[0][vy][vz] +
                                            G[0][vx][1] * Z2[1][vy][vz] +
                                            G[0][vx][2] * Z2[2][vy][vz];
-    kbc_gamma_relax<R>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c);
+    kbc_gamma_relax<R, GX>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c);
 }
 
-template <int S, int V>
+template <int S, int V, bool GX = false>
 __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
 {
     using R = typename Traits<S>::R;
@@ -517,9 +590,9 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         auto fneq_of = [&](int i) -> R { return fneq[i]; };
         if constexpr (is_central(V)) {
             const R uf[3] = {(R)u[0], (R)u[1], (R)u[2]};
-            kbc_relax_central<R, V>(f, d, uf, fneq_of, iCx, iA9, rho, c);
+            kbc_relax_central<R, V, GX>(f, d, uf, fneq_of, iCx, iA9, rho, c);
         } else {
-            kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, rho, c);
+            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, rho, c);
         }
     } else {
         // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ----
@@ -591,8 +664,10 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             if constexpr (DEV) return f[i] - (A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
             else return f[i] - A9[yz] * Cx[ax];
         };
-        if constexpr (is_central(V)) kbc_relax_central<R, V>(f, d, u, fneq_of, iCx, iA9, (double)rho, c);
-        else kbc_relax<R, V>(f, d, fneq_of, iCx, iA9, (double)rho, c);
+        if constexpr (is_central(V))
+            kbc_relax_central<R, V, GX>(f, d, u, fneq_of, iCx, iA9, (double)rho, c);
+        else
+            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, (double)rho, c);
     }
 }
 

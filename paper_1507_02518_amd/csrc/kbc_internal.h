@@ -19,7 +19,7 @@ enum Layout : int { LY_PULL = 0, LY_AA_EVEN = 1, LY_AA_ODD = 2 };
 void set_last_error(const char* msg);
 
 // One time step of one box (src -> dst for pull; in place for AA).
-hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p,
+hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
                        hipStream_t stream);
 
 // Write f^eq(rho, u) of device fields u [3][N], rho [N] (may be NULL) into the

@@ -54,7 +54,7 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
 //   AA odd:  read buf[26-i][x - v_i], write buf[i][x + v_i]
 // In both AA sweeps a node reads and writes the same 27 locations, so the
 // in-place update is free of races between nodes.
-template <int S, int V, int SW>
+template <int S, int V, int SW, bool GX = false>
 __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
                                             const Coll& c, const float* scale,
                                             const float* inv_scale, uint32_t n)
@@ -108,7 +108,7 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
         __builtin_amdgcn_sched_barrier(0);
     }
 
-    collide<S, V>(f, c);
+    collide<S, V, GX>(f, c);
 
     // AA odd sweep: store offsets x + v are formed after the collision, from
     // the coordinates alone, so they do not occupy registers across it (the
@@ -141,8 +141,8 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     }
 }
 
-// Fused step of one box: one thread per node.
-template <int S, int V, int SW>
+// Fused step of one box: one thread per node.  GX: exact stabilizer.
+template <int S, int V, int SW, bool GX>
 __global__ void __launch_bounds__(kStepBlock)
 #if KBC_WAVES_PER_EU
 __attribute__((amdgpu_waves_per_eu(KBC_WAVES_PER_EU, 8)))
@@ -151,7 +151,7 @@ k_step(StepParams p)
 {
     const uint32_t n = blockIdx.x * kStepBlock + threadIdx.x;
     if (n >= p.g.nnodes) return;
-    node_update<S, V, SW>(p.src, p.dst, p.g, p.c, p.scale, p.inv_scale, n);
+    node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale, p.inv_scale, n);
 }
 
 typedef __attribute__((address_space(1))) char gchar;
@@ -233,25 +233,37 @@ PoolFn pool_fn_v(int v, int sw)
 
 using StepFn = void (*)(StepParams);
 
-template <int S, int V>
+template <int S, int V, bool GX>
 constexpr StepFn step_fn(int sw)
 {
-    return sw == SW_PULL ? k_step<S, V, SW_PULL>
-                         : (sw == SW_AA_EVEN ? k_step<S, V, SW_AA_EVEN> : k_step<S, V, SW_AA_ODD>);
+    return sw == SW_PULL ? k_step<S, V, SW_PULL, GX>
+                         : (sw == SW_AA_EVEN ? k_step<S, V, SW_AA_EVEN, GX>
+                                             : k_step<S, V, SW_AA_ODD, GX>);
 }
 
-template <int S>
+template <int S, bool GX>
 StepFn step_fn_v(int v, int sw)
 {
     switch (v) {
-    case V_D: return step_fn<S, V_D>(sw);
-    case V_DT: return step_fn<S, V_DT>(sw);
-    case V_DQ: return step_fn<S, V_DQ>(sw);
-    case V_CD: return step_fn<S, V_CD>(sw);
-    case V_CDT: return step_fn<S, V_CDT>(sw);
-    case V_CDQ: return step_fn<S, V_CDQ>(sw);
-    case V_CDTQ: return step_fn<S, V_CDTQ>(sw);
-    default: return step_fn<S, V_DTQ>(sw);
+    case V_D: return step_fn<S, V_D, GX>(sw);
+    case V_DT: return step_fn<S, V_DT, GX>(sw);
+    case V_DQ: return step_fn<S, V_DQ, GX>(sw);
+    case V_CD: return step_fn<S, V_CD, GX>(sw);
+    case V_CDT: return step_fn<S, V_CDT, GX>(sw);
+    case V_CDQ: return step_fn<S, V_CDQ, GX>(sw);
+    case V_CDTQ: return step_fn<S, V_CDTQ, GX>(sw);
+    default: return step_fn<S, V_DTQ, GX>(sw);
+    }
+}
+
+template <bool GX>
+StepFn step_fn_sv(int storage, int v, int sw)
+{
+    switch (storage) {
+    case ST_F64: return step_fn_v<ST_F64, GX>(v, sw);
+    case ST_F32: return step_fn_v<ST_F32, GX>(v, sw);
+    case ST_F32X: return step_fn_v<ST_F32X, GX>(v, sw);
+    default: return step_fn_v<ST_F16, GX>(v, sw);
     }
 }
 
@@ -597,15 +609,11 @@ __global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_step(int storage, int variant, int sweep, const StepParams& p, hipStream_t stream)
+hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
+                       hipStream_t stream)
 {
-    StepFn fn;
-    switch (storage) {
-    case ST_F64: fn = step_fn_v<ST_F64>(variant, sweep); break;
-    case ST_F32: fn = step_fn_v<ST_F32>(variant, sweep); break;
-    case ST_F32X: fn = step_fn_v<ST_F32X>(variant, sweep); break;
-    default: fn = step_fn_v<ST_F16>(variant, sweep); break;
-    }
+    const StepFn fn = exact_gamma ? step_fn_sv<true>(storage, variant, sweep)
+                                  : step_fn_sv<false>(storage, variant, sweep);
     hipLaunchKernelGGL(fn, dim3((p.g.nnodes + kStepBlock - 1) / kStepBlock), dim3(kStepBlock), 0,
                        stream, p);
     return hipGetLastError();

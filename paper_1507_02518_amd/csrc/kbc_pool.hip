@@ -356,14 +356,18 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
     if (opt.variant < KBC_S_D || opt.variant > KBC_S_CDTQ) return pfail(KBC_EINVAL, "unknown variant");
     if (max_slots < 1 || max_slots > 65536) return pfail(KBC_EINVAL, "max_slots must be in [1, 65536]");
     if (hbm_budget_bytes < Arena::kGrain) return pfail(KBC_EINVAL, "budget below 64 KiB");
-    if (opt.gamma_fixed && !std::isfinite(opt.gamma_value))
+    if (opt.gamma_mode == KBC_GAMMA_EXACT)
+        return pfail(KBC_EINVAL, "the exact stabilizer is available for single boxes only");
+    if (opt.gamma_mode < KBC_GAMMA_ENTROPIC || opt.gamma_mode > KBC_GAMMA_FIXED)
+        return pfail(KBC_EINVAL, "unknown gamma_mode");
+    if (opt.gamma_mode == KBC_GAMMA_FIXED && !std::isfinite(opt.gamma_value))
         return pfail(KBC_EINVAL, "gamma_value must be finite");
 
     std::unique_ptr<kbc_pool> p(new (std::nothrow) kbc_pool());
     if (!p) return pfail(KBC_ENOMEM, "host allocation failed");
     p->dtype = dtype;
     p->variant = opt.variant;
-    p->defaults.gamma_fixed = opt.gamma_fixed ? 1 : 0;
+    p->defaults.gamma_fixed = opt.gamma_mode == KBC_GAMMA_FIXED ? 1 : 0;
     p->defaults.gamma_value = opt.gamma_value;
     p->defaults.gamma_eps = opt.gamma_eps > 0.0 ? opt.gamma_eps : (dtype == KBC_F64 ? 1e-28 : 1e-16);
     int dev = opt.device;

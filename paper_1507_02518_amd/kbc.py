@@ -29,6 +29,20 @@ F64, F32_DEV, F16_DEV, F32_DEV_X = 0, 1, 2, 3
 S_D, S_DT, S_DQ, S_DTQ = 0, 1, 2, 3
 S_CD, S_CDT, S_CDQ, S_CDTQ = 4, 5, 6, 7   # central-moment variants
 PULL, AA = 0, 1
+GAMMA_ENTROPIC, GAMMA_FIXED, GAMMA_EXACT = 0, 1, 2
+
+
+def _set_gamma(o, gamma):
+    """gamma: None -> entropic estimate; "exact" -> root of the entropy
+    condition; a number -> that fixed value."""
+    if gamma is None:
+        o.gamma_mode, o.gamma_value = GAMMA_ENTROPIC, 2.0
+    elif isinstance(gamma, str):
+        if gamma != "exact":
+            raise ValueError(f"gamma must be None, 'exact' or a number, not {gamma!r}")
+        o.gamma_mode, o.gamma_value = GAMMA_EXACT, 2.0
+    else:
+        o.gamma_mode, o.gamma_value = GAMMA_FIXED, float(gamma)
 
 DTYPES = {"f64": F64, "f32": F32_DEV, "f16": F16_DEV, "f32x": F32_DEV_X}
 
@@ -43,7 +57,7 @@ class kbc_options(ctypes.Structure):
     _fields_ = [
         ("variant", ctypes.c_int32),
         ("streaming", ctypes.c_int32),
-        ("gamma_fixed", ctypes.c_int32),
+        ("gamma_mode", ctypes.c_int32),
         ("device", ctypes.c_int32),
         ("gamma_value", ctypes.c_double),
         ("gamma_eps", ctypes.c_double),
@@ -322,8 +336,7 @@ class Box:
         o = kbc_options_default()
         o.variant = variant
         o.streaming = streaming
-        o.gamma_fixed = 0 if gamma is None else 1
-        o.gamma_value = 2.0 if gamma is None else float(gamma)
+        _set_gamma(o, gamma)
         o.gamma_eps = float(gamma_eps)
         o.device = device
         o.stream = stream
@@ -411,8 +424,7 @@ class Pool:
             dtype = DTYPES[dtype]
         o = kbc_options_default()
         o.variant = variant
-        o.gamma_fixed = 0 if gamma is None else 1
-        o.gamma_value = 2.0 if gamma is None else float(gamma)
+        _set_gamma(o, gamma)
         o.device = device
         o.stream = stream
         self.dtype = dtype

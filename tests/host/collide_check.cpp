@@ -1,8 +1,10 @@
 // Host check of the per-node collision the kernels run (kbc::collide, built
 // here for the CPU) against the oracle's seven-step collision, for the four
-// natural and the four central-moment variants: FP64 storage, and FP32
-// deviation storage with the FP64-formed non-equilibrium.  Prints the largest
-// differences and exits non-zero past the bounds given on the command line.
+// natural and the four central-moment variants: FP64 storage, FP32 deviation
+// storage with the FP64-formed non-equilibrium, and FP64 with the exact
+// stabilizer (root of Eq. result1) against the oracle's bisection.  Prints
+// the largest differences and exits non-zero past the bounds given on the
+// command line.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -15,12 +17,13 @@ int main(int argc, char** argv)
 {
     const double tol64 = argc > 1 ? std::atof(argv[1]) : 1e-15;
     const double tol32 = argc > 2 ? std::atof(argv[2]) : 1e-7;
+    const double tolx = argc > 3 ? std::atof(argv[3]) : 1e-14;
     std::mt19937_64 rng(2024);
     std::uniform_real_distribution<double> uu(-0.15, 0.15), rr(0.9, 1.1);
     std::normal_distribution<double> nn(0.0, 1.0);
     int fails = 0;
     for (int v = 0; v < 8; ++v) {
-        double e64 = 0.0, e32 = 0.0;
+        double e64 = 0.0, e32 = 0.0, ex = 0.0;
         for (int trial = 0; trial < 400; ++trial) {
             const double nu = trial % 2 ? 1e-4 : 5e-3;
             const double beta = kbco_beta_from_nu(nu);
@@ -29,8 +32,10 @@ int main(int argc, char** argv)
             kbco_feq(rr(rng), u, F);
             const double amp = trial % 3 == 0 ? 1e-5 : 0.02;
             for (int i = 0; i < 27; ++i) F[i] *= 1.0 + amp * nn(rng);
-            double P[27];
+            double P[27], PX[27];
             kbco_collide(F, beta, v, KBCO_GAMMA_ESTIMATE, 0.0, 1e-28, P, nullptr, nullptr,
+                         nullptr);
+            kbco_collide(F, beta, v, KBCO_GAMMA_EXACT, 0.0, 1e-28, PX, nullptr, nullptr,
                          nullptr);
 
             kbc::Coll c{};
@@ -38,10 +43,10 @@ int main(int argc, char** argv)
             c.inv_beta = 1.0 / beta;
             c.c2 = 2.0 - 1.0 / beta;
             c.gamma_fixed = 0;
-            double f[27];
+            double f[27], fx[27];
             float g[27];
             for (int i = 0; i < 27; ++i) {
-                f[i] = F[i];
+                f[i] = fx[i] = F[i];
                 g[i] = (float)(F[i] - kbc::weight(i));
             }
             c.gamma_eps = 1e-28;
@@ -54,6 +59,16 @@ int main(int argc, char** argv)
             case 5: kbc::collide<kbc::ST_F64, 5>(f, c); break;
             case 6: kbc::collide<kbc::ST_F64, 6>(f, c); break;
             default: kbc::collide<kbc::ST_F64, 7>(f, c); break;
+            }
+            switch (v) {
+            case 0: kbc::collide<kbc::ST_F64, 0, true>(fx, c); break;
+            case 1: kbc::collide<kbc::ST_F64, 1, true>(fx, c); break;
+            case 2: kbc::collide<kbc::ST_F64, 2, true>(fx, c); break;
+            case 3: kbc::collide<kbc::ST_F64, 3, true>(fx, c); break;
+            case 4: kbc::collide<kbc::ST_F64, 4, true>(fx, c); break;
+            case 5: kbc::collide<kbc::ST_F64, 5, true>(fx, c); break;
+            case 6: kbc::collide<kbc::ST_F64, 6, true>(fx, c); break;
+            default: kbc::collide<kbc::ST_F64, 7, true>(fx, c); break;
             }
             c.gamma_eps = 1e-16;
             switch (v) {
@@ -69,11 +84,12 @@ int main(int argc, char** argv)
             for (int i = 0; i < 27; ++i) {
                 e64 = std::fmax(e64, std::fabs(f[i] - P[i]));
                 e32 = std::fmax(e32, std::fabs((double)g[i] + kbc::weight(i) - P[i]));
+                ex = std::fmax(ex, std::fabs(fx[i] - PX[i]));
             }
         }
-        const bool ok = e64 <= tol64 && e32 <= tol32;
-        std::printf("variant %d: max|dP| FP64 %.3e  FP32-dev-X %.3e  %s\n", v, e64, e32,
-                    ok ? "ok" : "FAIL");
+        const bool ok = e64 <= tol64 && e32 <= tol32 && ex <= tolx;
+        std::printf("variant %d: max|dP| FP64 %.3e  FP32-dev-X %.3e  FP64 exact gamma %.3e  %s\n",
+                    v, e64, e32, ex, ok ? "ok" : "FAIL");
         if (!ok) ++fails;
     }
     return fails ? 1 : 0;

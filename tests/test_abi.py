@@ -42,7 +42,7 @@ def test_options_struct_layout_matches_header():
     int main(void) {
       printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(kbc_options),
              offsetof(kbc_options, variant), offsetof(kbc_options, streaming),
-             offsetof(kbc_options, gamma_fixed), offsetof(kbc_options, device),
+             offsetof(kbc_options, gamma_mode), offsetof(kbc_options, device),
              offsetof(kbc_options, gamma_value), offsetof(kbc_options, gamma_eps),
              offsetof(kbc_options, stream));
       return 0;
@@ -58,7 +58,7 @@ def test_options_struct_layout_matches_header():
                                                check=True).stdout.split()]
     O = kbc.kbc_options
     want = [ctypes.sizeof(O)] + [getattr(O, f).offset for f in
-                                 ("variant", "streaming", "gamma_fixed", "device",
+                                 ("variant", "streaming", "gamma_mode", "device",
                                   "gamma_value", "gamma_eps", "stream")]
     assert vals == want
 
@@ -66,7 +66,7 @@ def test_options_struct_layout_matches_header():
 def test_options_defaults():
     o = kbc.kbc_options_default()
     assert o.variant == kbc.S_DTQ and o.streaming == kbc.PULL
-    assert o.gamma_fixed == 0 and o.device == -1 and not o.stream
+    assert o.gamma_mode == kbc.GAMMA_ENTROPIC and o.device == -1 and not o.stream
 
 
 @pytest.mark.parametrize("shape,nu,dtype", [
@@ -98,6 +98,11 @@ def test_create_rejects_bad_options():
     o.streaming = 5
     with pytest.raises(kbc.KbcError):
         kbc.kbc_create((4, 4, 4), 1e-3, kbc.F64, o)
+    o = kbc.kbc_options_default()
+    o.gamma_mode = 3
+    with pytest.raises(kbc.KbcError) as e:
+        kbc.kbc_create((4, 4, 4), 1e-3, kbc.F64, o)
+    assert e.value.code == kbc.KBC_EINVAL
 
 
 def test_null_handles_are_rejected():
@@ -131,6 +136,11 @@ def test_pool_create_rejects_bad_arguments():
         with pytest.raises(kbc.KbcError) as e:
             kbc.kbc_pool_create(budget, dtype, None, slots, None)
         assert e.value.code == kbc.KBC_EINVAL
+    o = kbc.kbc_options_default()
+    o.gamma_mode = kbc.GAMMA_EXACT
+    with pytest.raises(kbc.KbcError) as e:
+        kbc.kbc_pool_create(1 << 30, kbc.F32_DEV, o, 8, None)
+    assert e.value.code == kbc.KBC_EINVAL and "single boxes" in kbc.kbc_last_error()
     lib = kbc.load()
     assert lib.kbc_pool_destroy(None) == kbc.KBC_OK
     assert lib.kbc_pool_advance(None, 1) == kbc.KBC_EINVAL
@@ -140,7 +150,9 @@ def test_device_collision_built_for_the_host_matches_the_oracle(orc):
     """kbc::collide (the kernels' per-node update, compiled here for the CPU)
     against the oracle's collision for all eight variants, natural and
     central: FP64 within 5e-15, FP32 deviation storage with FP64-formed
-    non-equilibrium within 3e-8 (measured 1.7e-15 and 7e-9)."""
+    non-equilibrium within 3e-8 (measured 1.7e-15 and 7e-9), and the exact
+    stabilizer (Newton on Eq. result1) against the oracle's bisection within
+    5e-15 (measured 1.7e-15; the exact and estimated gamma differ by ~3e-3)."""
     clang = "/opt/rocm/llvm/bin/clang++"
     if not os.path.exists(clang):
         pytest.skip("ROCm clang++ not present")
@@ -152,5 +164,5 @@ def test_device_collision_built_for_the_host_matches_the_oracle(orc):
                         os.path.join(ROOT, "tests", "host", "collide_check.cpp"),
                         "-L", odir, "-lkbc_oracle", f"-Wl,-rpath,{odir}", "-o", exe],
                        check=True, capture_output=True)
-        r = subprocess.run([exe, "5e-15", "3e-8"], capture_output=True, text=True)
+        r = subprocess.run([exe, "5e-15", "3e-8", "5e-15"], capture_output=True, text=True)
         assert r.returncode == 0, r.stdout + r.stderr

@@ -127,6 +127,30 @@ def test_forced_gamma_paths(orc, gamma_kind):
     assert err <= 1e-13
 
 
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+@pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
+def test_exact_entropic_gamma_matches_oracle(orc, streaming, variant):
+    """The exact stabilizer (root of Eq. result1 per node, Newton on the GPU,
+    bisection in the oracle): 16^3 Taylor-Green and a ragged box with a
+    density perturbation, 20 steps, element-wise; the run differs from the
+    estimate gamma* by far more than the tolerance."""
+    for shape, u, rho in [((16, 16, 16), inputs.taylor_green(16, 0.05), None),
+                          ((13, 7, 5), inputs.smooth_random((13, 7, 5), 0.06, seed=3),
+                           inputs.random_density((13, 7, 5), 0.02, seed=3))]:
+        nu = 1e-3
+        F = _oracle_run(orc, u, nu, 20, rho, variant=variant, exact=True)
+        Fe = _oracle_run(orc, u, nu, 20, rho, variant=variant)
+        with _box(shape, nu, variant=variant, streaming=streaming, gamma="exact") as b:
+            b.init_velocity(u, rho)
+            b.step(20)
+            f = b.populations()
+        err = np.abs(f - F).max()
+        gap = np.abs(Fe - F).max()
+        say(f"exact gamma {shape} variant={variant} streaming={streaming}: max|df| {err:.3e} "
+            f"(exact vs estimate {gap:.3e})")
+        assert err <= 1e-13 and gap > 1e3 * max(err, 1e-16)
+
+
 # ------------------------------------------------------ state handling ----
 
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
@@ -242,7 +266,7 @@ def test_step_before_init_is_a_state_error():
 
 # ------------------------------------------- full-size sampled parity ----
 
-def _lightcone_reference(orc, u, nodes, steps, nu, shape):
+def _lightcone_reference(orc, u, nodes, steps, nu, shape, **kw):
     """Oracle F(steps) at selected nodes: a (2 steps + 1)^3 block cut
     periodically around each node evolves exactly at its centre for
     `steps` steps (wrap-around data moves one node per step)."""
@@ -255,7 +279,7 @@ def _lightcone_reference(orc, u, nodes, steps, nu, shape):
         iy = (np.arange(y - r, y + r + 1)) % ny
         iz = (np.arange(z - r, z + r + 1)) % nz
         ub = u[:, iz][:, :, iy][:, :, :, ix]
-        F = _oracle_run(orc, np.ascontiguousarray(ub), nu, steps)
+        F = _oracle_run(orc, np.ascontiguousarray(ub), nu, steps, **kw)
         out.append(F[:, r, r, r])
     return np.array(out)
 
@@ -277,6 +301,23 @@ def test_full_size_fp64_sampled_against_oracle(orc, n, streaming):
     ref = _lightcone_reference(orc, u, nodes, steps, 5e-4, (n, n, n))
     err = np.abs(got - ref).max()
     say(f"full size {n}^3 streaming={streaming}: sampled max|df|={err:.3e}")
+    assert err <= 1e-14
+
+
+def test_full_size_exact_gamma_sampled_against_oracle(orc):
+    """256^3 decaying-turbulence start with the exact stabilizer (pull): two
+    GPU steps, 16 sampled nodes against the oracle's light-cone evolution."""
+    n = 256
+    u = inputs.hit(n, 4.0, 0.04, seed=1)
+    rng = np.random.default_rng(11)
+    nodes = rng.integers(0, n ** 3, size=16)
+    with _box(n, 5e-4, gamma="exact") as b:
+        b.init_velocity(u)
+        b.step(2)
+        got = b.sample(nodes)
+    ref = _lightcone_reference(orc, u, nodes, 2, 5e-4, (n, n, n), exact=True)
+    err = np.abs(got - ref).max()
+    say(f"full size 256^3 exact gamma: sampled max|df|={err:.3e}")
     assert err <= 1e-14
 
 
