@@ -145,6 +145,42 @@ int kbc_energy(kbc_handle h, double* k);
  * FP64, fixed reduction order.  Synchronises. */
 int kbc_enstrophy(kbc_handle h, double* omega);
 
+/* One-point statistics of section V.A for the velocity of F(t), all means
+ * over nodes, derivatives by central differences (order 2 or the nine-point
+ * eighth-order stencil the paper uses for its table of statistics), FP64,
+ * fixed reduction order:
+ *   k          = (1/2) <|u'|^2>
+ *   omega      = (1/2) <|curl u'|^2>
+ *   epsilon    = (nu/2) <(d_a u'_b + d_b u'_a)(d_a u'_b + d_b u'_a)>
+ *   div2       = <(div u)^2>  (epsilon - 2 nu omega = 2 nu div2 exactly)
+ *   dudx_moment[n-2] = <(d u'_x / dx)^n>, n = 2..6
+ *   skewness[n-3]    = (-1)^n <(du'_x/dx)^n> / <(du'_x/dx)^2>^(n/2), n = 3..6
+ * The derived turbulence, Taylor and Kolmogorov scales follow from k,
+ * epsilon and nu on the host. */
+typedef struct kbc_stats {
+    double k, omega, epsilon, div2;
+    double dudx_moment[5];
+    double skewness[4];
+} kbc_stats;
+
+/* Fill *out for the current state.  order: 2 or 8 (KBC_EINVAL otherwise).
+ * KBC_EUNSTABLE if the state is not finite.  Synchronises. */
+int kbc_statistics(kbc_handle h, int32_t order, kbc_stats* out);
+
+/* Statistics of the stabilizer gamma (section V.C) that the next step
+ * applies at each node (the collision evaluated on F(t), nothing written):
+ * out[0] mean, out[1] standard deviation, out[2] minimum, out[3] maximum
+ * over the nodes.  Follows the box's variant and gamma mode (a fixed gamma
+ * gives mean = gamma, std = 0).  Synchronises. */
+int kbc_gamma_statistics(kbc_handle h, double out[4]);
+
+/* Longitudinal and transversal velocity correlations along x (section
+ * V.B): rho11[r] = <u'_x(x) u'_x(x + r)> / <u'_x^2>,
+ * rho22[r] = <u'_y(x) u'_y(x + r)> / <u'_y^2>, r = 0..rmax (host arrays of
+ * rmax + 1).  Requires nx <= 4096 and 0 <= rmax < nx.  Allocates and frees
+ * a small device buffer.  Synchronises. */
+int kbc_correlation(kbc_handle h, int32_t rmax, double* rho11, double* rho22);
+
 /* Copy F(t) to host f [27][nz][ny][nx] FP64 (deviation storage is decoded
  * to full populations).  Synchronises. */
 int kbc_get_populations(kbc_handle h, double* f);

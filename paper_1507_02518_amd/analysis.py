@@ -40,3 +40,20 @@ def spectrum_error(E, E_ref, kmax=None):
     rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
     l2 = float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
     return {"max_rel": float(rel.max()), "l2_rel": l2, "shells": int(kmax)}
+
+
+def turbulence_scales(k: float, eps: float, nu: float) -> dict:
+    """Turbulence, Taylor and Kolmogorov scales of section V.A from the
+    kinetic energy k, the dissipation rate eps and the viscosity nu:
+    l0 = k^(3/2)/eps, u0 = k^(1/2), tau0 = l0/u0, Re0 = l0 u0/nu;
+    lambda = (15 nu u'^2/eps)^(1/2) with u' = (2k/3)^(1/2), tau_lambda =
+    lambda/u', Re_lambda = lambda u'/nu; eta = (nu^3/eps)^(1/4),
+    u_eta = (nu eps)^(1/4), tau_eta = (nu/eps)^(1/2)."""
+    l0 = k ** 1.5 / eps
+    u0 = k ** 0.5
+    up = (2.0 * k / 3.0) ** 0.5
+    lam = (15.0 * nu * up * up / eps) ** 0.5
+    return {"l0": l0, "u0": u0, "tau0": l0 / u0, "Re0": l0 * u0 / nu,
+            "lambda": lam, "u_lambda": up, "tau_lambda": lam / up, "Re_lambda": lam * up / nu,
+            "eta": (nu ** 3 / eps) ** 0.25, "u_eta": (nu * eps) ** 0.25,
+            "tau_eta": (nu / eps) ** 0.5}

@@ -78,7 +78,8 @@ struct kbc_box {
     double* d_u;
     double* d_rho;
     double* d_partial;
-    double* d_sum;      // [0..2] mean sums, [3..5] second reduction
+    double* d_sum;      // [0..2] mean sums, [3..5] second reduction, [8..15]
+                        // gradient statistics, [16..19] gamma statistics
     int* d_flag;
     unsigned* d_max;
     double* d_pop;      // canonical staging [27][N]
@@ -114,8 +115,8 @@ int ensure_diag(kbc_handle h, bool need_pop)
     const size_t N = h->g.nnodes;
     if (!h->d_u) KBC_HIP(hipMalloc(&h->d_u, 3 * N * sizeof(double)));
     if (!h->d_rho) KBC_HIP(hipMalloc(&h->d_rho, N * sizeof(double)));
-    if (!h->d_partial) KBC_HIP(hipMalloc(&h->d_partial, 3 * (size_t)reduce_partials() * sizeof(double)));
-    if (!h->d_sum) KBC_HIP(hipMalloc(&h->d_sum, 8 * sizeof(double)));
+    if (!h->d_partial) KBC_HIP(hipMalloc(&h->d_partial, 8 * (size_t)reduce_partials() * sizeof(double)));
+    if (!h->d_sum) KBC_HIP(hipMalloc(&h->d_sum, 32 * sizeof(double)));
     if (!h->d_flag) KBC_HIP(hipMalloc(&h->d_flag, sizeof(int)));
     if (!h->d_max) KBC_HIP(hipMalloc(&h->d_max, 27 * sizeof(unsigned)));
     if (need_pop && !h->d_pop) KBC_HIP(hipMalloc(&h->d_pop, 27 * N * sizeof(double)));
@@ -411,6 +412,86 @@ int kbc_enstrophy(kbc_handle h, double* omega)
     KBC_HIP(hipMemcpyAsync(&s, h->d_sum + 3, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     KBC_HIP(hipStreamSynchronize(h->stream));
     *omega = 0.5 * s / (double)h->g.nnodes;
+    return KBC_OK;
+}
+
+int kbc_statistics(kbc_handle h, int32_t order, kbc_stats* out)
+{
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(KBC_EINVAL, "out is NULL");
+    if (order != 2 && order != 8) return fail(KBC_EINVAL, "order must be 2 or 8");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    if (int r = compute_moments(h, false)) return r;
+    if (int r = mean_sums(h)) return r;
+    KBC_HIP(launch_reduce(1, h->g, h->d_u, h->d_sum, h->d_partial, h->d_sum + 3, h->stream));
+    KBC_HIP(launch_grad_stats(order, h->g, h->d_u, h->d_partial, h->d_sum + 8, h->stream));
+    double s[16];
+    KBC_HIP(hipMemcpyAsync(s, h->d_sum, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    const double N = (double)h->g.nnodes;
+    out->k = 0.5 * s[3] / N;
+    out->omega = 0.5 * s[8] / N;
+    out->epsilon = 0.5 * h->nu * s[9] / N;
+    out->div2 = s[10] / N;
+    for (int n = 0; n < 5; ++n) out->dudx_moment[n] = s[11 + n] / N;
+    const double m2 = out->dudx_moment[0];
+    for (int n = 3; n <= 6; ++n)
+        out->skewness[n - 3] = ((n % 2) ? -1.0 : 1.0) * out->dudx_moment[n - 2] / std::pow(m2, 0.5 * n);
+    return KBC_OK;
+}
+
+int kbc_gamma_statistics(kbc_handle h, double out[4])
+{
+    if (int r = check_handle(h)) return r;
+    if (!out) return fail(KBC_EINVAL, "out is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if (int r = set_device(h)) return r;
+    if (int r = ensure_diag(h, false)) return r;
+    KBC_HIP(launch_gamma_stats(h->dtype, h->variant, h->exact_gamma, layout_now(h), state_buf(h),
+                               h->g, h->coll, h->inv_scale, h->d_partial, h->d_sum + 16,
+                               h->stream));
+    double s[4];
+    KBC_HIP(hipMemcpyAsync(s, h->d_sum + 16, sizeof(s), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    const double N = (double)h->g.nnodes;
+    const double mean = s[0] / N;
+    out[0] = mean;
+    out[1] = std::sqrt(std::max(0.0, s[1] / N - mean * mean));
+    out[2] = s[2];
+    out[3] = s[3];
+    if (!std::isfinite(mean)) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
+    return KBC_OK;
+}
+
+int kbc_correlation(kbc_handle h, int32_t rmax, double* rho11, double* rho22)
+{
+    if (int r = check_handle(h)) return r;
+    if (!rho11 || !rho22) return fail(KBC_EINVAL, "rho11 or rho22 is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
+    if ((int)h->g.nx > corr_max_nx()) return fail(KBC_EINVAL, "nx above the correlation limit (4096)");
+    if (rmax < 0 || rmax >= (int)h->g.nx || rmax >= corr_max_lags())
+        return fail(KBC_EINVAL, "rmax must be in [0, nx)");
+    if (int r = set_device(h)) return r;
+    if (int r = compute_moments(h, false)) return r;
+    if (int r = mean_sums(h)) return r;
+    const size_t L2 = 2 * (size_t)(rmax + 1);
+    double* part = nullptr;
+    double* dout = nullptr;
+    KBC_HIP(hipMalloc(&part, (size_t)corr_blocks(h->g) * L2 * sizeof(double)));
+    hipError_t e = hipMalloc(&dout, L2 * sizeof(double));
+    std::vector<double> host(L2);
+    if (e == hipSuccess) e = launch_corr_x(h->g, h->d_u, h->d_sum, rmax, part, dout, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host.data(), dout, L2 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(part);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) return fail(KBC_EDEVICE, hipGetErrorString(e));
+    for (int r = 0; r <= rmax; ++r) {
+        rho11[r] = host[2 * r] / host[0];
+        rho22[r] = host[2 * r + 1] / host[1];
+    }
     return KBC_OK;
 }
 

@@ -328,7 +328,7 @@ __host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, Ife
 template <typename R, bool GX, typename DsFn, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of, FneqFn fneq_of,
                                                          const R (&iCx)[3], const R (&iA9)[9],
-                                                         double rho, const Coll& c)
+                                                         double rho, const Coll& c, double* gout)
 {
     // --- 5-6. dh and the entropic scalar products --------------------------
     R sh = R(0), hh = R(0);
@@ -362,6 +362,8 @@ __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of,
         }
     }
 
+    if (gout) *gout = (double)gamma;
+
     // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
     // dh = (f - f^eq) - ds as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
     const R c1 = R(c.beta) * (R(2) - gamma);
@@ -378,7 +380,7 @@ __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of,
 template <typename R, int V, bool GX, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d, FneqFn fneq_of,
                                                    const R (&iCx)[3], const R (&iA9)[9],
-                                                   double rho, const Coll& c)
+                                                   double rho, const Coll& c, double* gout)
 {
     constexpr bool WT = with_t(V);
     constexpr bool WQ = with_q(V);
@@ -413,7 +415,7 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
         }
         return R(sx * sy * sz) * qC;
     };
-    kbc_gamma_relax<R, GX>(f, ds_of, fneq_of, iCx, iA9, rho, c);
+    kbc_gamma_relax<R, GX>(f, ds_of, fneq_of, iCx, iA9, rho, c, gout);
 }
 
 // Steps 3-7 for the central-moment variants (section IV; appendix).  The
@@ -433,7 +435,7 @@ template <typename R, int V, bool GX, typename FneqFn>
 __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMom<R>& d,
                                                            const R (&u)[3], FneqFn fneq_of,
                                                            const R (&iCx)[3], const R (&iA9)[9],
-                                                           double rho, const Coll& c)
+                                                           double rho, const Coll& c, double* gout)
 {
     constexpr bool WT = with_t(V);
     constexpr bool WQ = with_q(V);
@@ -507,11 +509,13 @@ __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMo
                 ds[vx + 3 * vy + 9 * vz] = G[0][vx][0] * Z2[0][vy][vz] +
                                            G[0][vx][1] * Z2[1][vy][vz] +
                                            G[0][vx][2] * Z2[2][vy][vz];
-    kbc_gamma_relax<R, GX>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c);
+    kbc_gamma_relax<R, GX>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c, gout);
 }
 
+// gout, when given, receives the gamma used at this node.
 template <int S, int V, bool GX = false>
-__host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c)
+__host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27], const Coll& c,
+                                                 double* gout = nullptr)
 {
     using R = typename Traits<S>::R;
     constexpr bool DEV = Traits<S>::kDev;
@@ -590,9 +594,9 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         auto fneq_of = [&](int i) -> R { return fneq[i]; };
         if constexpr (is_central(V)) {
             const R uf[3] = {(R)u[0], (R)u[1], (R)u[2]};
-            kbc_relax_central<R, V, GX>(f, d, uf, fneq_of, iCx, iA9, rho, c);
+            kbc_relax_central<R, V, GX>(f, d, uf, fneq_of, iCx, iA9, rho, c, gout);
         } else {
-            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, rho, c);
+            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, rho, c, gout);
         }
     } else {
         // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ----
@@ -665,9 +669,9 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             else return f[i] - A9[yz] * Cx[ax];
         };
         if constexpr (is_central(V))
-            kbc_relax_central<R, V, GX>(f, d, u, fneq_of, iCx, iA9, (double)rho, c);
+            kbc_relax_central<R, V, GX>(f, d, u, fneq_of, iCx, iA9, (double)rho, c, gout);
         else
-            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, (double)rho, c);
+            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, (double)rho, c, gout);
     }
 }
 

@@ -65,6 +65,27 @@ hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t str
 //   kind 0: out[0..2] = sum_x u_a(x)
 //   kind 1: out[0]    = sum_x |u(x) - mean|^2     (mean = in[0..2] / N)
 //   kind 2: out[0]    = sum_x |curl_FD2 u(x)|^2
+// Flow statistics.  grad: out[8] = sums over nodes of |curl u|^2,
+// sum_ab (d_a u_b + d_b u_a)^2, (div u)^2, (du_x/dx)^n for n = 2..6, with the
+// central stencil of the given order (2 or 8); partial: reduce_partials() * 8.
+hipError_t launch_grad_stats(int order, const Geom& g, const double* u, double* partial,
+                             double* out, hipStream_t stream);
+// gamma of the next collision at every node: out[4] = sum, sum of squares,
+// min, max; partial: reduce_partials() * 4.
+hipError_t launch_gamma_stats(int storage, int variant, bool exact_gamma, int layout,
+                              const void* buf, const Geom& g, const Coll& c,
+                              const float* inv_scale, double* partial, double* out,
+                              hipStream_t stream);
+// x-correlation sums: out[2r + c] = sum over nodes of u'_c(x) u'_c(x + r),
+// c = 0 (x component), 1 (y component), r = 0..rmax; requires
+// nx <= corr_max_nx(), rmax < corr_max_lags(); partial: corr_blocks(g) *
+// 2 (rmax + 1) doubles; mean_sum: the three sums of u.
+int corr_max_nx();
+int corr_max_lags();
+int corr_blocks(const Geom& g);
+hipError_t launch_corr_x(const Geom& g, const double* u, const double* mean_sum, int rmax,
+                         double* partial, double* out, hipStream_t stream);
+
 // `partial` is device scratch of reduce_partials() doubles * 3.
 int reduce_partials();
 hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double* mean_sum,

@@ -572,6 +572,260 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double* __restric
     block_sum<3>(acc, out);
 }
 
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_reduce_final_k(const double* __restrict__ partial,
+                                                           int count, double* __restrict__ out)
+{
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += partial[K * b + k];
+    block_sum<K>(acc, out);
+}
+
+// ---------------------------------------------------------------------------
+// Flow statistics of section V from the velocity field u[3][N].
+// ---------------------------------------------------------------------------
+
+// (a + d) mod n for any small signed d
+__device__ __forceinline__ uint32_t wrap_mod(uint32_t a, int d, uint32_t n)
+{
+    int64_t v = ((int64_t)a + d) % (int64_t)n;
+    return (uint32_t)(v < 0 ? v + n : v);
+}
+
+// Central first-derivative weights of f(x+m) - f(x-m): second order, and
+// the nine-point eighth-order stencil.
+template <int ORD> struct FdW;
+template <> struct FdW<2> {
+    static constexpr int M = 1;
+    __device__ static constexpr double c(int) { return 0.5; }
+};
+template <> struct FdW<8> {
+    static constexpr int M = 4;
+    __device__ static constexpr double c(int m)
+    {
+        return m == 1 ? 4.0 / 5.0 : (m == 2 ? -1.0 / 5.0 : (m == 3 ? 4.0 / 105.0 : -1.0 / 280.0));
+    }
+};
+
+// Per-block sums of |curl u|^2, sum_ab (d_a u_b + d_b u_a)^2, (div u)^2 and
+// (du_x/dx)^n for n = 2..6 (grid-stride, fixed order).
+template <int ORD>
+__global__ void __launch_bounds__(kBlock) k_grad_stats(Geom g, const double* __restrict__ u,
+                                                       double* __restrict__ partial)
+{
+    const size_t N = g.nnodes;
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.nnodes; n += gridDim.x * kBlock) {
+        uint32_t x, y, z;
+        node_xyz(n, g, x, y, z);
+        double G[3][3];  // G[a][b] = d u_a / d x_b
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint32_t np[FdW<ORD>::M], nm[FdW<ORD>::M];
+#pragma unroll
+            for (int m = 1; m <= FdW<ORD>::M; ++m) {
+                if (b == 0) {
+                    np[m - 1] = node_of(wrap_mod(x, m, g.nx), y, z, g);
+                    nm[m - 1] = node_of(wrap_mod(x, -m, g.nx), y, z, g);
+                } else if (b == 1) {
+                    np[m - 1] = node_of(x, wrap_mod(y, m, g.ny), z, g);
+                    nm[m - 1] = node_of(x, wrap_mod(y, -m, g.ny), z, g);
+                } else {
+                    np[m - 1] = node_of(x, y, wrap_mod(z, m, g.nz), g);
+                    nm[m - 1] = node_of(x, y, wrap_mod(z, -m, g.nz), g);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double d = 0.0;
+#pragma unroll
+                for (int m = 1; m <= FdW<ORD>::M; ++m)
+                    d += FdW<ORD>::c(m) * (u[a * N + np[m - 1]] - u[a * N + nm[m - 1]]);
+                G[a][b] = d;
+            }
+        }
+        const double wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
+        acc[0] += wx * wx + wy * wy + wz * wz;
+        double e = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double sab = G[a][b] + G[b][a];
+                e += sab * sab;
+            }
+        acc[1] += e;
+        const double dv = G[0][0] + G[1][1] + G[2][2];
+        acc[2] += dv * dv;
+        const double d1 = G[0][0], d2 = d1 * d1, d3 = d2 * d1;
+        acc[3] += d2;
+        acc[4] += d3;
+        acc[5] += d2 * d2;
+        acc[6] += d3 * d2;
+        acc[7] += d3 * d3;
+    }
+    block_sum<8>(acc, partial + 8 * blockIdx.x);
+}
+
+// Per-block sums of gamma and gamma^2 and the block's min and max of the
+// stabilizer that the next step would use at each node (the collision up to
+// step 6 on the stored state; nothing is written back).
+template <int S, int V, bool GX>
+__global__ void __launch_bounds__(kBlock) k_gamma_stats(int layout, const void* buf, Geom g, Coll c,
+                                                        LoadCtx lc, double* __restrict__ partial)
+{
+    using T = typename Traits<S>::T;
+    using R = typename Traits<S>::R;
+    double sum = 0.0, sum2 = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.nnodes; n += gridDim.x * kBlock) {
+        uint32_t x, y, z;
+        node_xyz(n, g, x, y, z);
+        R f[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            int slot;
+            uint32_t node;
+            locate(layout, i, x, y, z, g, slot, node);
+            f[i] = decode<S>(static_cast<const T*>(buf)[slot * g.plane + node], lc.inv_scale[slot]);
+        }
+        double gam = 0.0;
+        collide<S, V, GX>(f, c, &gam);
+        sum += gam;
+        sum2 += gam * gam;
+        lo = fmin(lo, gam);
+        hi = fmax(hi, gam);
+    }
+    double acc[2] = {sum, sum2};
+    block_sum<2>(acc, partial + 4 * blockIdx.x);
+    __shared__ double mn[kBlock / 64], mx[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        mn[wave] = lo;
+        mx[wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kBlock / 64; ++w) {
+            lo = fmin(lo, mn[w]);
+            hi = fmax(hi, mx[w]);
+        }
+        // the block sums went to partial[4b], [4b+1]; min and max follow
+        partial[4 * blockIdx.x + 2] = lo;
+        partial[4 * blockIdx.x + 3] = hi;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gamma_final(const double* __restrict__ partial,
+                                                        int count, double* __restrict__ out)
+{
+    double acc[2] = {0.0, 0.0};
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (int b = threadIdx.x; b < count; b += kBlock) {
+        acc[0] += partial[4 * b];
+        acc[1] += partial[4 * b + 1];
+        lo = fmin(lo, partial[4 * b + 2]);
+        hi = fmax(hi, partial[4 * b + 3]);
+    }
+    double tmp[2];
+    block_sum<2>(acc, tmp);  // thread 0 holds the sums in tmp
+    __shared__ double mn[kBlock / 64], mx[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        mn[wave] = lo;
+        mx[wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kBlock / 64; ++w) {
+            lo = fmin(lo, mn[w]);
+            hi = fmax(hi, mx[w]);
+        }
+        out[0] = tmp[0];
+        out[1] = tmp[1];
+        out[2] = lo;
+        out[3] = hi;
+    }
+}
+
+// Sums over the (y, z) lines of u'_c(x) u'_c(x + r) for c = x, y components
+// and r = 0..rmax.  A block stages one line at a time in LDS; thread t owns
+// the lags r = t, t + kBlock, ... (at most kCorrLags per thread) for all the
+// lines the block visits, so the per-block sums come out in a fixed order.
+constexpr int kCorrLags = 8;
+constexpr int kCorrMaxN = 4096;
+
+__global__ void __launch_bounds__(kBlock) k_corr_x(Geom g, const double* __restrict__ u,
+                                                   const double* __restrict__ mean_sum, int rmax,
+                                                   double* __restrict__ partial)
+{
+    __shared__ double line[2][kCorrMaxN];
+    const size_t N = g.nnodes;
+    const double mx = mean_sum[0] / (double)N, my = mean_sum[1] / (double)N;
+    double acc[2][kCorrLags];
+#pragma unroll
+    for (int k = 0; k < kCorrLags; ++k) acc[0][k] = acc[1][k] = 0.0;
+    const uint32_t lines = g.ny * g.nz;
+    for (uint32_t l = blockIdx.x; l < lines; l += gridDim.x) {
+        const size_t base = (size_t)l * g.nx;
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < g.nx; x += kBlock) {
+            line[0][x] = u[base + x] - mx;
+            line[1][x] = u[N + base + x] - my;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCorrLags; ++k) {
+            const int r = threadIdx.x + k * kBlock;
+            if (r > rmax) break;
+            double s0 = 0.0, s1 = 0.0;
+            uint32_t xr = (uint32_t)r % g.nx;
+            for (uint32_t x = 0; x < g.nx; ++x) {
+                s0 += line[0][x] * line[0][xr];
+                s1 += line[1][x] * line[1][xr];
+                xr = xr + 1 == g.nx ? 0u : xr + 1;
+            }
+            acc[0][k] += s0;
+            acc[1][k] += s1;
+        }
+    }
+    const int L = rmax + 1;
+#pragma unroll
+    for (int k = 0; k < kCorrLags; ++k) {
+        const int r = threadIdx.x + k * kBlock;
+        if (r < L) {
+            partial[((size_t)blockIdx.x * L + r) * 2] = acc[0][k];
+            partial[((size_t)blockIdx.x * L + r) * 2 + 1] = acc[1][k];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_corr_final(const double* __restrict__ partial,
+                                                       int blocks, int rmax, double* __restrict__ out)
+{
+    const int L = rmax + 1;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 2 * L) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * 2 * L + t];
+    out[t] = s;  // out[2r + c]
+}
+
 inline unsigned grid_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
 
 __global__ void k_zero_u32(unsigned* p, int n)
@@ -747,6 +1001,81 @@ hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_stats(int order, const Geom& g, const double* u, double* partial,
+                             double* out, hipStream_t stream)
+{
+    const unsigned blocks = std::min<unsigned>(kReduceBlocks, grid_for(g.nnodes));
+    if (order == 8) hipLaunchKernelGGL(k_grad_stats<8>, dim3(blocks), dim3(kBlock), 0, stream, g, u, partial);
+    else hipLaunchKernelGGL(k_grad_stats<2>, dim3(blocks), dim3(kBlock), 0, stream, g, u, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final_k<8>, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+namespace {
+using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
+
+template <int S, bool GX>
+GammaFn gamma_fn_v(int v)
+{
+    switch (v) {
+    case V_D: return k_gamma_stats<S, V_D, GX>;
+    case V_DT: return k_gamma_stats<S, V_DT, GX>;
+    case V_DQ: return k_gamma_stats<S, V_DQ, GX>;
+    case V_CD: return k_gamma_stats<S, V_CD, GX>;
+    case V_CDT: return k_gamma_stats<S, V_CDT, GX>;
+    case V_CDQ: return k_gamma_stats<S, V_CDQ, GX>;
+    case V_CDTQ: return k_gamma_stats<S, V_CDTQ, GX>;
+    default: return k_gamma_stats<S, V_DTQ, GX>;
+    }
+}
+
+template <bool GX>
+GammaFn gamma_fn(int storage, int v)
+{
+    switch (storage) {
+    case ST_F64: return gamma_fn_v<ST_F64, GX>(v);
+    case ST_F32: return gamma_fn_v<ST_F32, GX>(v);
+    case ST_F32X: return gamma_fn_v<ST_F32X, GX>(v);
+    default: return gamma_fn_v<ST_F16, GX>(v);
+    }
+}
+}  // namespace
+
+hipError_t launch_gamma_stats(int storage, int variant, bool exact_gamma, int layout,
+                              const void* buf, const Geom& g, const Coll& c,
+                              const float* inv_scale, double* partial, double* out,
+                              hipStream_t stream)
+{
+    LoadCtx lc;
+    for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
+    const unsigned blocks = std::min<unsigned>(kReduceBlocks, grid_for(g.nnodes));
+    const GammaFn fn = exact_gamma ? gamma_fn<true>(storage, variant) : gamma_fn<false>(storage, variant);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, layout, buf, g, c, lc, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gamma_final, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+int corr_max_nx() { return kCorrMaxN; }
+int corr_max_lags() { return kCorrLags * kBlock; }
+int corr_blocks(const Geom& g) { return (int)std::min<uint32_t>(kReduceBlocks, g.ny * g.nz); }
+
+hipError_t launch_corr_x(const Geom& g, const double* u, const double* mean_sum, int rmax,
+                         double* partial, double* out, hipStream_t stream)
+{
+    const int blocks = corr_blocks(g);
+    hipLaunchKernelGGL(k_corr_x, dim3(blocks), dim3(kBlock), 0, stream, g, u, mean_sum, rmax, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int L2 = 2 * (rmax + 1);
+    hipLaunchKernelGGL(k_corr_final, dim3((L2 + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                       partial, blocks, rmax, out);
     return hipGetLastError();
 }
 

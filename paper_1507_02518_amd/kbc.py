@@ -53,6 +53,17 @@ class KbcError(RuntimeError):
         self.code = code
 
 
+class kbc_stats(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("epsilon", ctypes.c_double),
+        ("div2", ctypes.c_double),
+        ("dudx_moment", ctypes.c_double * 5),
+        ("skewness", ctypes.c_double * 4),
+    ]
+
+
 class kbc_options(ctypes.Structure):
     _fields_ = [
         ("variant", ctypes.c_int32),
@@ -92,6 +103,9 @@ def load():
         "kbc_moments": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p]),
         "kbc_energy": (ctypes.c_int, [_H, _D]),
         "kbc_enstrophy": (ctypes.c_int, [_H, _D]),
+        "kbc_statistics": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(kbc_stats)]),
+        "kbc_gamma_statistics": (ctypes.c_int, [_H, ctypes.c_void_p]),
+        "kbc_correlation": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
         "kbc_get_populations": (ctypes.c_int, [_H, ctypes.c_void_p]),
         "kbc_set_populations": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_int64]),
         "kbc_sample_populations": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_int64,
@@ -202,6 +216,26 @@ def kbc_enstrophy(h: int) -> float:
     w = ctypes.c_double()
     _check(load().kbc_enstrophy(h, ctypes.byref(w)), "kbc_enstrophy")
     return w.value
+
+
+def kbc_statistics(h: int, order: int = 8) -> dict:
+    st = kbc_stats()
+    _check(load().kbc_statistics(h, int(order), ctypes.byref(st)), "kbc_statistics")
+    return {"k": st.k, "omega": st.omega, "epsilon": st.epsilon, "div2": st.div2,
+            "dudx_moments": {n: st.dudx_moment[n - 2] for n in range(2, 7)},
+            "skewness": {n: st.skewness[n - 3] for n in range(3, 7)}}
+
+
+def kbc_gamma_statistics(h: int) -> dict:
+    out = np.zeros(4)
+    _check(load().kbc_gamma_statistics(h, _p(out)), "kbc_gamma_statistics")
+    return {"mean": out[0], "std": out[1], "min": out[2], "max": out[3]}
+
+
+def kbc_correlation(h: int, rmax: int):
+    r11, r22 = np.zeros(rmax + 1), np.zeros(rmax + 1)
+    _check(load().kbc_correlation(h, int(rmax), _p(r11), _p(r22)), "kbc_correlation")
+    return r11, r22
 
 
 def kbc_get_populations(h: int, f_out):
@@ -370,6 +404,15 @@ class Box:
 
     def enstrophy(self) -> float:
         return kbc_enstrophy(self.h)
+
+    def statistics(self, order: int = 8) -> dict:
+        return kbc_statistics(self.h, order)
+
+    def gamma_statistics(self) -> dict:
+        return kbc_gamma_statistics(self.h)
+
+    def correlation(self, rmax: int):
+        return kbc_correlation(self.h, rmax)
 
     def populations(self):
         f = np.empty((27,) + self._field_shape())

@@ -166,3 +166,26 @@ def test_device_collision_built_for_the_host_matches_the_oracle(orc):
                        check=True, capture_output=True)
         r = subprocess.run([exe, "5e-15", "3e-8", "5e-15"], capture_output=True, text=True)
         assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_stats_struct_layout_matches_header():
+    src = r"""
+    #include <stddef.h>
+    #include <stdio.h>
+    #include "kbc.h"
+    int main(void) {
+      printf("%zu %zu %zu %zu\n", sizeof(kbc_stats), offsetof(kbc_stats, div2),
+             offsetof(kbc_stats, dudx_moment), offsetof(kbc_stats, skewness));
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        exe = os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split()]
+    S = kbc.kbc_stats
+    assert vals == [ctypes.sizeof(S), S.div2.offset, S.dudx_moment.offset, S.skewness.offset]
