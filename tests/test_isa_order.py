@@ -46,7 +46,8 @@ def _kernels(asm, pattern):
 
 def test_aa_step_kernels_load_everything_before_storing(asm):
     ks = _kernels(asm, r"k_stepILi\dELi\dELi[12]E")
-    assert len(ks) == 4 * 4 * 2
+    # 4 storage forms x 8 variants x 2 sweeps x (estimate, exact gamma)
+    assert len(ks) == 4 * 8 * 2 * 2
     for nm, ops in ks.items():
         assert len(ops) == 54, (nm, len(ops))
         first_store = next(i for i, op in enumerate(ops) if "store" in op)
@@ -74,7 +75,7 @@ def test_pool_kernels_load_everything_before_storing(asm):
     different basic blocks (the instruction scheduler never moves code
     between blocks); inside any block no load may follow a store."""
     names = re.findall(r"^(_ZN3kbc\S*k_pool_stepILi\dELi\dELi[12]E\S*):", asm, flags=re.M)
-    assert len(names) == 4 * 4 * 2
+    assert len(names) == 4 * 8 * 2
     for nm in names:
         blocks = _blocks(asm, nm)
         seq = [op for b in blocks for op in b]

@@ -108,19 +108,20 @@ def test_lattice_symmetry_equivariance(orc, variant):
         assert np.abs(ub - op(ua)).max() < 1e-13
 
 
-@pytest.mark.parametrize("variant", [3, 7])
-def test_kbc_stays_stable_where_lbgk_fails(orc, variant):
+@pytest.mark.parametrize("variant,n,steps", [(3, 16, 250), (7, 12, 150)])
+def test_kbc_stays_stable_where_lbgk_fails(orc, variant, n, steps):
     """Under-resolved decaying turbulence at very low viscosity: the entropic
     stabilizer keeps the run finite and dissipative while LBGK (gamma = 2)
-    diverges, the contrast of section V (natural and central s)."""
-    u = inputs.hit(16, 2.0, 0.05, seed=0)
+    diverges, the contrast of section V (natural and central s; the central
+    case on a smaller box, its oracle being the slower one)."""
+    u = inputs.hit(n, 2.0, 0.05, seed=0)
     F0 = orc.init_feq(u)
     beta = orc.beta_from_nu(1e-5)
     _, u0 = orc.macros(F0)
     k0 = orc.energy(u0)
     with np.errstate(all="ignore"):
-        Fk = orc.run(F0, beta, 250, variant=variant)
-        Fl = orc.run(F0, beta, 250, gamma=2.0)
+        Fk = orc.run(F0, beta, steps, variant=variant)
+        Fl = orc.run(F0, beta, steps, gamma=2.0)
         _, uk = orc.macros(Fk)
         _, ul = orc.macros(Fl)
         kk, kl = orc.energy(uk), orc.energy(ul)
