@@ -90,9 +90,18 @@ struct StepParams {
     void* dst;
     Geom g;
     Coll c;
-    float scale[27];      // FP16 storage: stored = (f - W) * scale
-    float inv_scale[27];
+    // FP16 storage: stored = (f - W) * 2^scale_exp[i]; zero for the other forms
+    int8_t scale_exp[28];
 };
+
+__host__ __device__ __forceinline__ float ldexp_(float x, int e)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_ldexpf(x, e);
+#else
+    return __builtin_ldexpf(x, e);
+#endif
+}
 
 __device__ inline void node_xyz(uint32_t n, const Geom& g, uint32_t& x, uint32_t& y, uint32_t& z)
 {
@@ -139,6 +148,23 @@ template <int S>
 __device__ __forceinline__ typename Traits<S>::R decode(typename Traits<S>::T v, float inv_scale)
 {
     if constexpr (S == ST_F16) return (float)v * inv_scale;
+    else return v;
+}
+
+// The step kernels scale FP16 deviations by powers of two held as exponents
+// (a byte per direction rather than two floats): ldexp equals the
+// multiplication by 2^e exactly, so both codecs give the same bits.
+template <int S>
+__device__ __forceinline__ typename Traits<S>::R decode_exp(typename Traits<S>::T v, int e)
+{
+    if constexpr (S == ST_F16) return ldexp_((float)v, -e);
+    else return v;
+}
+
+template <int S>
+__device__ __forceinline__ typename Traits<S>::T encode_exp(typename Traits<S>::R v, int e)
+{
+    if constexpr (S == ST_F16) return (_Float16)ldexp_(v, e);
     else return v;
 }
 

@@ -102,7 +102,7 @@ struct PoolBox {
     uint32_t ntiles;      // ceil(nnodes / (block * sub))
     int32_t parity0;      // t mod 2 at the start of the batch
     int32_t steps;        // steps the box takes in the current batch
-    float scale[27], inv_scale[27];
+    int8_t scale_exp[28]; // FP16 storage: stored = (f - W) * 2^scale_exp[i]
 };
 
 struct PoolMeta {

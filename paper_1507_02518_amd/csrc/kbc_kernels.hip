@@ -26,6 +26,9 @@ constexpr int kBlock = 256;
 #ifndef KBC_WAVES_PER_EU
 #define KBC_WAVES_PER_EU 0
 #endif
+#ifndef KBC_NT_LOAD
+#define KBC_NT_LOAD 0
+#endif
 constexpr int kStepBlock = KBC_STEP_BLOCK;
 
 template <typename T>
@@ -56,8 +59,7 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
 // in-place update is free of races between nodes.
 template <int S, int V, int SW, bool GX = false>
 __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
-                                            const Coll& c, const float* scale,
-                                            const float* inv_scale, uint32_t n)
+                                            const Coll& c, const int8_t* sexp, uint32_t n)
 {
     using T = typename Traits<S>::T;
     using R = typename Traits<S>::R;
@@ -77,11 +79,18 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     const uint32_t bz[3] = {zp * planexyb, z * planexyb, zm * planexyb};
     const uint32_t nb = n * EB;
 
-    const char* __restrict__ src = static_cast<const char*>(srcv);
-    char* __restrict__ dst = static_cast<char*>(dstv);
+    // Loads and stores go through two pointers, which in the AA sweeps hold
+    // the same buffer; they carry no restrict qualifier, and the order of the
+    // accesses comes from the scheduling barrier below.  (One pointer for
+    // both measured slower: in the even sweep the compiler stops addressing
+    // through scalar plane bases, in the odd FP16 sweep it schedules worse.)
+    const char* src = static_cast<const char*>(srcv);
+    char* dst = static_cast<char*>(dstv);
     const uint64_t planeb = g.plane * EB;
     auto ld = [&](int slot, uint32_t off) -> T {
-        return *reinterpret_cast<const T*>(src + slot * planeb + off);
+        const T* p = reinterpret_cast<const T*>(src + slot * planeb + off);
+        if constexpr (KBC_NT_LOAD) return __builtin_nontemporal_load(p);
+        else return *p;
     };
     auto st = [&](int slot, uint32_t off, T v) {
         st_pop(reinterpret_cast<T*>(dst + slot * planeb + off), v);
@@ -92,11 +101,11 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            f[i] = decode<S>(ld(i, bz[az] + by[ay] + bx[ax]), inv_scale[i]);
+            f[i] = decode_exp<S>(ld(i, bz[az] + by[ay] + bx[ax]), sexp[i]);
         } else if constexpr (SW == SW_AA_EVEN) {
-            f[i] = decode<S>(ld(i, nb), inv_scale[i]);
+            f[i] = decode_exp<S>(ld(i, nb), sexp[i]);
         } else {
-            f[i] = decode<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), inv_scale[opp(i)]);
+            f[i] = decode_exp<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), sexp[opp(i)]);
         }
     }
 
@@ -132,11 +141,11 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            st(i, nb, encode<S>(f[i], scale[i]));
+            st(i, nb, encode_exp<S>(f[i], sexp[i]));
         } else if constexpr (SW == SW_AA_EVEN) {
-            st(opp(i), nb, encode<S>(f[i], scale[opp(i)]));
+            st(opp(i), nb, encode_exp<S>(f[i], sexp[opp(i)]));
         } else {
-            st(i, fz[az] + fy[ay] + fx[ax], encode<S>(f[i], scale[i]));
+            st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], sexp[i]));
         }
     }
 }
@@ -151,7 +160,7 @@ k_step(StepParams p)
 {
     const uint32_t n = blockIdx.x * kStepBlock + threadIdx.x;
     if (n >= p.g.nnodes) return;
-    node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale, p.inv_scale, n);
+    node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
 }
 
 typedef __attribute__((address_space(1))) char gchar;
@@ -183,6 +192,14 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
         }
         const PoolBox& b = boxes[lo];
         if (k >= b.steps) continue;
+        // FP16: the box's scale exponents, staged in LDS once per tile so the
+        // node update reads them there rather than from the box table
+        __shared__ int8_t s_exp[28];
+        if constexpr (S == ST_F16) {
+            __syncthreads();
+            if (threadIdx.x < 28) s_exp[threadIdx.x] = b.scale_exp[threadIdx.x];
+            __syncthreads();
+        }
         // the box's constants as values, so the population stores cannot be
         // taken to alias them
         const Geom g = b.g;
@@ -202,7 +219,7 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
                 gchar* dbuf = gbuf;
                 asm volatile("" : "+s"(sbuf));
                 asm volatile("" : "+s"(dbuf));
-                node_update<S, V, SW>((void*)sbuf, (void*)dbuf, g, c, b.scale, b.inv_scale, n);
+                node_update<S, V, SW>((void*)sbuf, (void*)dbuf, g, c, s_exp, n);
             }
         }
     }
@@ -834,28 +851,19 @@ __global__ void k_zero_u32(unsigned* p, int n)
     if (i < n) p[i] = 0u;
 }
 
-// Streaming copy: each thread moves four 16-byte words per iteration, the
-// four loads issued before the stores; the grid covers the array once when
-// it can (one block per 16 KiB).
+// Streaming copy: one 16-byte word per thread and iteration (ordinary
+// loads, non-temporal stores); the grid covers up to 2^21 blocks, which is
+// the whole array for copies up to 8 GiB.  This form measured fastest among
+// the copies tried (16 B or 8 B per lane, 1 or 4 words per thread, with or
+// without non-temporal loads).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
                                                   const u32x4* __restrict__ src, size_t n16)
 {
-    const size_t stride = (size_t)gridDim.x * kBlock * 4;
-    for (size_t base = (size_t)blockIdx.x * kBlock * 4 + threadIdx.x; base < n16; base += stride) {
-        u32x4 v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const size_t k = base + (size_t)j * kBlock;
-            if (k < n16) v[j] = __builtin_nontemporal_load(&src[k]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const size_t k = base + (size_t)j * kBlock;
-            if (k < n16) __builtin_nontemporal_store(v[j], &dst[k]);
-        }
-    }
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n16; k += stride)
+        __builtin_nontemporal_store(src[k], &dst[k]);
 }
 
 }  // namespace
@@ -982,8 +990,8 @@ hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& 
 hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t stream)
 {
     if (n16 == 0) return hipSuccess;
-    const size_t want = (n16 + 4 * kBlock - 1) / (4 * kBlock);
-    const unsigned blocks = (unsigned)std::min<size_t>(want, 1u << 20);
+    const size_t want = (n16 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)std::min<size_t>(want, 1u << 21);
     hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<u32x4*>(dst),
                        static_cast<const u32x4*>(src), n16);
     return hipGetLastError();

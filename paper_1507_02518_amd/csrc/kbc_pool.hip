@@ -125,6 +125,7 @@ struct Slot {
     int64_t target = 0;     // steps requested
     std::shared_ptr<Event> last;
     float scale[27], inv_scale[27];
+    int8_t scale_exp[28];
 };
 
 struct LaunchCfg {
@@ -511,6 +512,7 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
     s.bytes = bytes;
     s.target = steps;
     for (int i = 0; i < 27; ++i) s.scale[i] = s.inv_scale[i] = 1.0f;
+    std::memset(s.scale_exp, 0, sizeof(s.scale_exp));
     auto undo = [&](int code) {
         p->arena.release(off, bytes);
         return code;
@@ -543,6 +545,7 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
             const int ex = (int)std::floor(std::log2(4096.0 / m));
             s.scale[i] = std::ldexp(1.0f, ex);
             s.inv_scale[i] = std::ldexp(1.0f, -ex);
+            s.scale_exp[i] = (int8_t)ex;
         }
     }
     e = launch_init_feq(p->dtype, LY_AA_EVEN, buf, s.g, s.scale, p->d_stage, nullptr, p->admit_stream);
@@ -599,8 +602,8 @@ static int pool_advance(kbc_pool_handle p, int64_t g, const int32_t* only, int32
         b.ntiles = (s.g.nnodes + tile_nodes - 1) / tile_nodes;
         b.parity0 = (int32_t)(s.t & 1);
         b.steps = (int32_t)steps;
-        std::memcpy(b.scale, s.scale, sizeof(b.scale));
-        std::memcpy(b.inv_scale, s.inv_scale, sizeof(b.inv_scale));
+        static_assert(sizeof(b.scale_exp) == sizeof(s.scale_exp), "exponent layout");
+        std::memcpy(b.scale_exp, s.scale_exp, sizeof(b.scale_exp));
         tiles[grp] += b.ntiles;
         batch = std::max(batch, steps);
         node_steps += (double)s.g.nnodes * (double)steps;
