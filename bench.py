@@ -136,7 +136,7 @@ def ensemble_and_serving(kbc, args):
         log("[bench] ensemble: 64 boxes, edges {24..96}, 500 steps, FP32 storage")
         boxes = serve.ensemble_boxes(64, seed=0)
         # warm-up, in which the launch-shape tuner measures its candidates
-        serve.run_ensemble(boxes[:16], kbc.F32_DEV_X, batched=True, g=10, tune_cache=cache)
+        serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=True, g=10, tune_cache=cache)
         pool = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=True, tune_cache=cache)
         loop = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=False)
         same = all(pool["results"][i] == loop["results"][i] for i in pool["results"])

@@ -221,9 +221,13 @@ int kbc_stream(kbc_handle h, void** stream);
  * hipGraph), so boxes admitted while others run share the GPU from their
  * first step on.  Each box evolves exactly as the same box alone (same
  * kernels, same arithmetic), so results do not depend on the mix.  Launch
- * shape (tile = block size, persistent grid size) comes from an online
- * autotuner that times its candidates on the first batches of real work and
- * keeps the fastest per dtype and variant in tune_cache (may be NULL).
+ * shape (threads per block, blocks: one per tile or a persistent grid,
+ * block-sized sub-tiles per tile) comes from an online autotuner.  Batches
+ * are classed by floor(log2(mean nodes per box)); the first batches of a new
+ * class time each of 12 candidate shapes twice on real work, and the fastest
+ * is kept for that class (and per dtype and variant in the text file
+ * tune_cache, which may be NULL).  Batches of a class still being measured
+ * by another round run one block per tile, 256 threads. 
  * ------------------------------------------------------------------------ */
 typedef struct kbc_pool* kbc_pool_handle;
 
@@ -272,14 +276,15 @@ int kbc_pool_release(kbc_pool_handle p, int32_t slot);
 /* Wait for every enqueued batch. */
 int kbc_pool_sync(kbc_pool_handle p);
 
-/* Arena bytes in use, resident boxes, current launch shape (threads per
- * block; blocks, 0 meaning one block per tile; block-sized sub-tiles per
- * tile) and whether the tuner is still measuring (any pointer may be NULL). */
+/* Arena bytes in use, resident boxes, the launch shape of the latest batch
+ * (threads per block; blocks, 0 meaning one block per tile; block-sized
+ * sub-tiles per tile) and whether a tuning round is in progress (any pointer
+ * may be NULL). */
 int kbc_pool_info(kbc_pool_handle p, size_t* bytes_used, int32_t* boxes, int32_t* block,
                   int32_t* grid, int32_t* sub, int32_t* tuning);
 
-/* Fix the launch shape (block: 64..512 in steps of 64; grid >= 0, 0 for
- * one block per tile; sub in 1..64) and stop tuning. */
+/* Fix the launch shape for every batch (block: 64..512 in steps of 64;
+ * grid >= 0, 0 for one block per tile; sub in 1..64) and stop tuning. */
 int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid, int32_t sub);
 
 /* Measurement utility (not part of the method): copy `bytes` (a multiple of

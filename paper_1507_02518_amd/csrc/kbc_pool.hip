@@ -160,10 +160,13 @@ struct kbc_pool {
     hipEvent_t mirror_ev[2] = {nullptr, nullptr};
     bool mirror_used[2] = {false, false};
     int mirror = 0;
-    std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;
-    std::vector<std::tuple<int64_t, int, int>> graph_order;
-    LaunchCfg cfg{256, 1024, 4};
-    bool tuning = false;
+    std::map<std::tuple<int64_t, int, int, int>, hipGraphExec_t> graphs;
+    std::vector<std::tuple<int64_t, int, int, int>> graph_order;
+    LaunchCfg cfg{256, 0, 1};          // the configuration of the latest batch
+    bool fixed = false;                // set by kbc_pool_set_launch
+    std::map<int, LaunchCfg> tuned;    // box-size bucket -> chosen configuration
+    bool tuning = false;               // a tuning round is in progress
+    int tune_bucket = -1;              // the bucket it measures
     std::vector<LaunchCfg> cands;
     std::vector<double> cand_cost;
     size_t cand_next = 0;
@@ -212,10 +215,13 @@ int ensure_diag(kbc_pool* p, size_t nnodes)
     return KBC_OK;
 }
 
-std::string cache_key(const kbc_pool* p)
+// Tuned configurations are kept per workload class: the bucket of a batch is
+// floor(log2(mean nodes per box)), since the best tile and grid shape differ
+// between many small boxes and a few large ones.
+std::string cache_prefix(const kbc_pool* p)
 {
     std::ostringstream os;
-    os << "gfx950 dtype=" << p->dtype << " variant=" << p->variant;
+    os << "gfx950 dtype=" << p->dtype << " variant=" << p->variant << " bucket=";
     return os.str();
 }
 
@@ -223,18 +229,18 @@ void load_tune_cache(kbc_pool* p)
 {
     if (p->tune_cache.empty()) return;
     std::ifstream in(p->tune_cache);
-    std::string line, key = cache_key(p);
+    std::string line;
+    const std::string pre = cache_prefix(p);
     while (std::getline(in, line)) {
         const size_t bar = line.find('|');
-        if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+        if (bar == std::string::npos || line.compare(0, pre.size(), pre) != 0) continue;
+        std::istringstream key(line.substr(pre.size(), bar - pre.size()));
         std::istringstream rest(line.substr(bar + 1));
-        int block = 0, grid = 0;
-        int sub = 0;
-        if (rest >> block >> grid >> sub && block >= 64 && block <= kPoolMaxBlock && block % 64 == 0 &&
-            grid >= 0 && sub >= 1 && sub <= 64) {
-            p->cfg = LaunchCfg{block, grid, sub};
-            p->tuning = false;
-        }
+        int bucket = -1, block = 0, grid = 0, sub = 0;
+        if (key >> bucket && rest >> block >> grid >> sub && bucket >= 0 && bucket < 40 &&
+            block >= 64 && block <= kPoolMaxBlock && block % 64 == 0 && grid >= 0 && sub >= 1 &&
+            sub <= 64)
+            p->tuned[bucket] = LaunchCfg{block, grid, sub};
     }
 }
 
@@ -242,15 +248,18 @@ void save_tune_cache(kbc_pool* p)
 {
     if (p->tune_cache.empty()) return;
     std::vector<std::string> keep;
+    const std::string pre = cache_prefix(p);
     {
         std::ifstream in(p->tune_cache);
-        std::string line, key = cache_key(p);
+        std::string line;
         while (std::getline(in, line))
-            if (line.substr(0, line.find('|')) != key && !line.empty()) keep.push_back(line);
+            if (!line.empty() && line.compare(0, pre.size(), pre) != 0) keep.push_back(line);
     }
     std::ofstream out(p->tune_cache, std::ios::trunc);
     for (auto& l : keep) out << l << "\n";
-    out << cache_key(p) << "|" << p->cfg.block << " " << p->cfg.grid << " " << p->cfg.sub << "\n";
+    for (auto& kv : p->tuned)
+        out << pre << kv.first << "|" << kv.second.block << " " << kv.second.grid << " "
+            << kv.second.sub << "\n";
 }
 
 // Collect a finished timing measurement of the online tuner, if any.
@@ -266,11 +275,13 @@ void tuner_collect(kbc_pool* p, bool wait)
         slot = std::min(slot, cost);
     }
     p->timing_pending = false;
-    if (p->cand_next >= p->cands.size()) {
+    // every candidate is timed twice (the first batch of a new graph also
+    // uploads it); the better of the two counts
+    if (p->cand_next >= 2 * p->cands.size()) {
         size_t best = 0;
         for (size_t i = 1; i < p->cands.size(); ++i)
             if (p->cand_cost[i] < p->cand_cost[best]) best = i;
-        p->cfg = p->cands[best];
+        p->tuned[p->tune_bucket] = p->cands[best];
         p->tuning = false;
         save_tune_cache(p);
     }
@@ -283,10 +294,12 @@ void destroy_graphs(kbc_pool* p)
     p->graph_order.clear();
 }
 
-int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, hipGraphExec_t* out)
+// groups: bit g set when parity group g holds a box in this batch; a group
+// that is empty for the whole batch gets no launches.
+int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, int groups, hipGraphExec_t* out)
 {
     // the sub-tile count lives in the uploaded table, not in the graph
-    const auto key = std::make_tuple(steps, cfg.block, cfg.grid);
+    const auto key = std::make_tuple(steps, cfg.block, cfg.grid, groups);
     auto it = p->graphs.find(key);
     if (it != p->graphs.end()) {
         *out = it->second;
@@ -304,11 +317,14 @@ int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, hipGraphExec_t* out)
     for (int64_t k = 0; k < steps && err == hipSuccess; ++k) {
         // group (k mod 2) is at even parity at step k, the other group odd
         const int ge = (int)(k & 1), go = 1 - ge;
-        err = launch_pool_step(p->dtype, p->variant, SW_AA_EVEN, p->d_boxes[ge], p->d_tstart[ge],
-                               p->d_meta[ge], (int)k, cfg.block, cfg.grid, p->stream);
-        if (err == hipSuccess)
-            err = launch_pool_step(p->dtype, p->variant, SW_AA_ODD, p->d_boxes[go], p->d_tstart[go],
-                                   p->d_meta[go], (int)k, cfg.block, cfg.grid, p->stream);
+        if (groups & (1 << ge))
+            err = launch_pool_step(p->dtype, p->variant, SW_AA_EVEN, p->d_boxes[ge],
+                                   p->d_tstart[ge], p->d_meta[ge], (int)k, cfg.block, cfg.grid,
+                                   p->stream);
+        if (err == hipSuccess && (groups & (1 << go)))
+            err = launch_pool_step(p->dtype, p->variant, SW_AA_ODD, p->d_boxes[go],
+                                   p->d_tstart[go], p->d_meta[go], (int)k, cfg.block, cfg.grid,
+                                   p->stream);
     }
     const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
     if (err != hipSuccess) {
@@ -428,7 +444,7 @@ int kbc_pool_create(size_t hbm_budget_bytes, int32_t dtype, const kbc_options* o
         for (int mult : {0, 16})
             for (int sub : {1, 2, 4}) p->cands.push_back(LaunchCfg{block, mult * p->cus, sub});
     p->cand_cost.assign(p->cands.size(), 1e300);
-    p->tuning = true;
+    p->tuning = false;   // rounds start per box-size bucket, on first use
     if (tune_cache) p->tune_cache = tune_cache;
     load_tune_cache(p.get());
     *out = p.release();
@@ -573,12 +589,37 @@ static int pool_advance(kbc_pool_handle p, int64_t g, const int32_t* only, int32
     PHIP(hipSetDevice(p->device));
     // while tuning, each batch times one candidate: wait for the previous one
     tuner_collect(p, p->tuning);
-    LaunchCfg cfg = p->cfg;
-    int cand = -1;
-    if (p->tuning && !p->timing_pending && p->cand_next < p->cands.size()) {
-        cand = (int)p->cand_next++;
-        cfg = p->cands[cand];
+    // the batch's workload class
+    double sel_nodes = 0.0;
+    int sel_boxes = 0;
+    for (size_t si = 0; si < p->slots.size(); ++si) {
+        const Slot& s = p->slots[si];
+        if (!s.used || s.t >= s.target || (only && !pick[si])) continue;
+        sel_nodes += (double)s.g.nnodes;
+        ++sel_boxes;
     }
+    const int bucket =
+        sel_boxes ? std::max(0, (int)std::floor(std::log2(sel_nodes / sel_boxes))) : 0;
+    LaunchCfg cfg{256, 0, 1};
+    int cand = -1;
+    if (p->fixed) {
+        cfg = p->cfg;
+    } else if (p->tuned.count(bucket)) {
+        cfg = p->tuned[bucket];
+    } else if (sel_boxes) {
+        if (!p->tuning) {
+            p->tuning = true;
+            p->tune_bucket = bucket;
+            p->cand_next = 0;
+            p->cand_cost.assign(p->cands.size(), 1e300);
+        }
+        if (p->tune_bucket == bucket && !p->timing_pending &&
+            p->cand_next < 2 * p->cands.size()) {
+            cand = (int)(p->cand_next++ % p->cands.size());
+            cfg = p->cands[cand];
+        }
+    }
+    p->cfg = cfg;
     const uint32_t tile_nodes = (uint32_t)(cfg.block * cfg.sub);
     // per-group box tables for this batch
     const int m = p->mirror;
@@ -632,7 +673,8 @@ static int pool_advance(kbc_pool_handle p, int64_t g, const int32_t* only, int32
     hipGraphExec_t exec = nullptr;
     LaunchCfg gcfg = cfg;
     gcfg.grid = launch_grid(cfg, std::max(tiles[0], tiles[1]));
-    if (int r = get_graph(p, batch, gcfg, &exec)) return r;
+    const int groups = (count[0] ? 1 : 0) | (count[1] ? 2 : 0);
+    if (int r = get_graph(p, batch, gcfg, groups, &exec)) return r;
     if (cand >= 0) PHIP(hipEventRecord(p->tev0, p->stream));
     PHIP(hipGraphLaunch(exec, p->stream));
     if (cand >= 0) {
@@ -750,6 +792,7 @@ int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid, int32_t 
         return pfail(KBC_EINVAL, "block must be 64..512 in steps of 64, grid >= 0, sub in 1..64");
     tuner_collect(p, true);
     p->cfg = LaunchCfg{block, grid, sub};
+    p->fixed = true;
     p->tuning = false;
     return KBC_OK;
 }
