@@ -393,16 +393,17 @@ def test_deviation_storage_error_against_oracle(orc, dtype, tol_k, tol_f, stream
 
 
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
-def test_hit128_fp64_series_matches_oracle_over_1000_steps(streaming):
-    """128^3 decaying HIT (k0 = 4, u_rms = 0.04, nu = 5e-4, seed 1): k(t) and
-    Omega(t) every 10 steps for 1000 steps against the oracle's stored
+def test_hit128_fp64_series_matches_oracle_over_2000_steps(streaming):
+    """128^3 decaying HIT (k0 = 4, u_rms = 0.04, nu = 5e-4, seed 1), the full
+    2000 steps: k(t) and Omega(t) every 10 steps against the oracle's stored
     series (tests/golden/oracle_hit128_series.txt)."""
     ref = np.loadtxt(os.path.join(GOLDEN, "oracle_hit128_series.txt"))
+    assert ref.shape[0] == 2001
     u = inputs.hit(128, 4.0, 0.04, seed=1)
     ek, ew = [], []
     with _box(128, 5e-4, streaming=streaming) as b:
         b.init_velocity(u)
-        for t in range(0, 1001, 10):
+        for t in range(0, 2001, 10):
             if t:
                 b.step(10)
             ek.append(abs(b.energy() / ref[t, 1] - 1))
