@@ -57,6 +57,8 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
 //   AA odd:  read buf[26-i][x - v_i], write buf[i][x + v_i]
 // In both AA sweeps a node reads and writes the same 27 locations, so the
 // in-place update is free of races between nodes.
+typedef __attribute__((address_space(1))) char gchar_t;
+
 template <int S, int V, int SW, bool GX = false>
 __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
                                             const Coll& c, const int8_t* sexp, uint32_t n)
@@ -87,25 +89,46 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     const char* src = static_cast<const char*>(srcv);
     char* dst = static_cast<char*>(dstv);
     const uint64_t planeb = g.plane * EB;
+    // Where every plane is accessed at the same offset (the loads and stores
+    // of the even AA sweep, the stores of the pull sweep) the compiler would
+    // fold buffer + offset into one 64-bit vector address and add each
+    // plane's distance with 64-bit vector arithmetic, two VALU instructions
+    // per access.  Hiding the plane base (a scalar) keeps the scalar-base +
+    // 32-bit-offset form, as for the shifted accesses.  The base passes
+    // through a global-address-space pointer so that the compiler still
+    // knows the accesses are global rather than flat.
+    auto plane = [&](auto* b, int slot, bool hide) {
+        auto* p = b + slot * planeb;
+        if (hide) {
+            gchar_t* q = (gchar_t*)p;
+            asm volatile("" : "+s"(q));
+            p = (decltype(p))q;
+        }
+        return p;
+    };
     auto ld = [&](int slot, uint32_t off) -> T {
-        const T* p = reinterpret_cast<const T*>(src + slot * planeb + off);
+        const T* p = reinterpret_cast<const T*>(plane(src, slot, SW == SW_AA_EVEN) + off);
         if constexpr (KBC_NT_LOAD) return __builtin_nontemporal_load(p);
         else return *p;
     };
     auto st = [&](int slot, uint32_t off, T v) {
-        st_pop(reinterpret_cast<T*>(dst + slot * planeb + off), v);
+        st_pop(reinterpret_cast<T*>(plane(dst, slot, SW != SW_AA_ODD) + off), v);
     };
+
+    // FP16 scale exponent of direction i: the host makes it equal for i and
+    // its opposite, so 14 distinct values (scalar registers) serve all 27
+    auto ex = [&](int i) -> int { return sexp[i <= 13 ? i : 26 - i]; };
 
     R f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            f[i] = decode_exp<S>(ld(i, bz[az] + by[ay] + bx[ax]), sexp[i]);
+            f[i] = decode_exp<S>(ld(i, bz[az] + by[ay] + bx[ax]), ex(i));
         } else if constexpr (SW == SW_AA_EVEN) {
-            f[i] = decode_exp<S>(ld(i, nb), sexp[i]);
+            f[i] = decode_exp<S>(ld(i, nb), ex(i));
         } else {
-            f[i] = decode_exp<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), sexp[opp(i)]);
+            f[i] = decode_exp<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), ex(i));
         }
     }
 
@@ -141,11 +164,11 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     for (int i = 0; i < 27; ++i) {
         const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
         if constexpr (SW == SW_PULL) {
-            st(i, nb, encode_exp<S>(f[i], sexp[i]));
+            st(i, nb, encode_exp<S>(f[i], ex(i)));
         } else if constexpr (SW == SW_AA_EVEN) {
-            st(opp(i), nb, encode_exp<S>(f[i], sexp[opp(i)]));
+            st(opp(i), nb, encode_exp<S>(f[i], ex(i)));
         } else {
-            st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], sexp[i]));
+            st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
         }
     }
 }
