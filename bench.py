@@ -319,6 +319,7 @@ def main():
                                   ("f32devx_pull", kbc.F32_DEV_X, kbc.PULL, None),
                                   ("f32devx_aa", kbc.F32_DEV_X, kbc.AA, None),
                                   ("f16dev_aa", kbc.F16_DEV, kbc.AA, None),
+                                  ("f16dev_pull", kbc.F16_DEV, kbc.PULL, None),
                                   ("f64_pull_s_d", kbc.F64, kbc.PULL, kbc.S_D),
                                   ("f64_pull_central", kbc.F64, kbc.PULL, C),
                                   ("f32devx_pull_central", kbc.F32_DEV_X, kbc.PULL, C),

@@ -223,9 +223,16 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     h->g.nnodes = (uint32_t)(shape[0] * shape[1] * shape[2]);
     h->g.dnx = make_fastdiv(h->g.nx);
     h->g.dny = make_fastdiv(h->g.ny);
-    // distance between direction planes: the node count plus a pad that keeps
-    // the 27 read and 27 write streams off a common power-of-two stride
-    h->g.plane = h->g.nnodes + plane_pad_elems(h->g.nnodes, elem_bytes(dtype), opt.streaming);
+    // Pull boxes whose whole lattice lies within 4 GiB (the step kernels'
+    // 32-bit offsets) are x-blocked: the 27 populations of 64 (or 32) nodes
+    // adjacent in x are contiguous, which measured 5% faster than planes for
+    // the FP64 pull step (and the same for AA, which stays in planes).
+    // Otherwise planes, spaced by the node count plus a pad that keeps the
+    // 27 read and 27 write streams off a common power-of-two stride.
+    if (opt.streaming == KBC_PULL && 27.0 * nn * (double)elem_bytes(dtype) < 4294967296.0)
+        geom_blocked(h->g);
+    else
+        geom_planes(h->g, plane_pad_elems(h->g.nnodes, elem_bytes(dtype), opt.streaming));
     h->dtype = dtype;
     h->variant = opt.variant;
     h->streaming = opt.streaming;
@@ -267,7 +274,7 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
         }
         h->own_stream = true;
     }
-    const size_t bytes = 27ull * h->g.plane * elem_bytes(dtype);
+    const size_t bytes = geom_extent(h->g) * elem_bytes(dtype);
     const int nbuf = h->streaming == KBC_PULL ? 2 : 1;
     for (int b = 0; b < nbuf; ++b) {
         e = hipMalloc(&h->buf[b], bytes);

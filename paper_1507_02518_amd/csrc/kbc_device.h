@@ -67,12 +67,30 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f)
     return (hi + n) >> f.s;
 }
 
-// Geometry of one periodic box inside a population buffer.
+// Geometry of one periodic box inside a population buffer, and where
+// population slot s of node (x, y, z) sits in it: element
+//   s * plane + z * slab + y * row + (x >> xshift) * chunk + (x & xmask).
+// Two layouts use this form:
+//   planes    [27][nz][ny][nx] (plane >= nnodes, row = nx, slab = nx*ny,
+//             xshift = 31, so a row is one chunk and x & xmask = x);
+//   x-blocked [nz][ny][nx/B][27][B] (plane = B, chunk = 27 B, row = 27 nx,
+//             slab = 27 nx ny, B = 2^xshift, xmask = B - 1; with B = nx and
+//             xshift = 31 for rows that no power of two >= 32 divides).
 struct Geom {
     uint32_t nx, ny, nz, nnodes;   // nnodes = nx*ny*nz
     FastDiv dnx, dny;
-    uint64_t plane;                // elements between consecutive directions
+    uint64_t plane;                // elements between consecutive slots
+    uint32_t row, slab;            // elements between y and z neighbours
+    uint32_t chunk;                // elements between consecutive x-chunks
+    uint32_t xshift, xmask;        // chunk and position of x in it
 };
+
+__host__ __device__ __forceinline__ uint64_t pop_index(const Geom& g, int slot, uint32_t x,
+                                                       uint32_t y, uint32_t z)
+{
+    return (uint64_t)slot * g.plane + (uint64_t)z * g.slab + (uint64_t)y * g.row +
+           (uint64_t)(x >> g.xshift) * g.chunk + (x & g.xmask);
+}
 
 // Per-box collision constants.
 struct Coll {

@@ -15,6 +15,49 @@ namespace kbc {
 //   AA:    even t: F_i(x, t) = buf[i][x]; odd t: F_i(x, t) = buf[26-i][x - v_i].
 enum Layout : int { LY_PULL = 0, LY_AA_EVEN = 1, LY_AA_ODD = 2 };
 
+// Population layouts of a box (see Geom).  Planes [27][nz][ny][nx], each
+// followed by `pad` unused elements:
+inline void geom_planes(Geom& g, uint64_t pad)
+{
+    g.plane = (uint64_t)g.nnodes + pad;
+    g.row = g.nx;
+    g.slab = g.nx * g.ny;
+    g.chunk = 0;
+    g.xshift = 31;
+    g.xmask = 0x7fffffffu;
+}
+
+// x-blocked [nz][ny][nx/B][27][B]: the 27 populations of B nodes adjacent in
+// x lie in one contiguous run, B = 64 or 32 where it divides nx, else B = nx.
+inline void geom_blocked(Geom& g)
+{
+    const uint32_t b = g.nx % 64 == 0 ? 64 : (g.nx % 32 == 0 ? 32 : g.nx);
+    g.plane = b;
+    g.row = 27 * g.nx;
+    g.slab = 27 * g.nx * g.ny;
+    if (b == g.nx) {
+        g.chunk = 0;
+        g.xshift = 31;
+        g.xmask = 0x7fffffffu;
+    } else {
+        g.chunk = 27 * b;
+        g.xshift = b == 64 ? 6 : 5;
+        g.xmask = b - 1;
+    }
+}
+
+inline bool geom_is_planes(const Geom& g) { return g.row == g.nx && g.xshift == 31 && g.plane >= g.nnodes; }
+
+// Elements of the buffer that the layout spans.
+inline uint64_t geom_extent(const Geom& g) { return pop_index(g, 26, g.nx - 1, g.ny - 1, g.nz - 1) + 1; }
+
+// Bytes spanned by the populations of one slot (the 32-bit offsets of the
+// step kernels address within this span from the slot's base).
+inline uint64_t geom_slot_span_bytes(const Geom& g, size_t elem)
+{
+    return (pop_index(g, 0, g.nx - 1, g.ny - 1, g.nz - 1) + 1) * elem;
+}
+
 // Record the message returned by kbc_last_error() on this thread.
 void set_last_error(const char* msg);
 

@@ -71,15 +71,21 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     constexpr uint32_t EB = sizeof(T);
     uint32_t x, y, z;
     node_xyz(n, g, x, y, z);
-    const uint32_t rowb = g.nx * EB, planexyb = g.ny * g.nx * EB;
+    const uint32_t rowb = g.row * EB, slabb = g.slab * EB;
+    // Pull boxes may be x-blocked (see Geom); AA boxes are always laid out
+    // in planes, where the offset of x in its row is x itself.
+    auto xoff = [&](uint32_t xx) -> uint32_t {
+        if constexpr (SW == SW_PULL) return (xx >> g.xshift) * (g.chunk * EB) + (xx & g.xmask) * EB;
+        else return xx * EB;
+    };
     const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
     const uint32_t ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
     const uint32_t zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
     // byte offset of coordinate x - v along each axis, indexed by v + 1
-    const uint32_t bx[3] = {xp * EB, x * EB, xm * EB};
+    const uint32_t bx[3] = {xoff(xp), xoff(x), xoff(xm)};
     const uint32_t by[3] = {yp * rowb, y * rowb, ym * rowb};
-    const uint32_t bz[3] = {zp * planexyb, z * planexyb, zm * planexyb};
-    const uint32_t nb = n * EB;
+    const uint32_t bz[3] = {zp * slabb, z * slabb, zm * slabb};
+    const uint32_t nb = SW == SW_PULL ? bz[1] + by[1] + bx[1] : n * EB;
 
     // Loads and stores go through two pointers, which in the AA sweeps hold
     // the same buffer; they carry no restrict qualifier, and the order of the
@@ -149,15 +155,15 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     if constexpr (SW == SW_AA_ODD) {
         uint32_t x2 = x, y2 = y, z2 = z;
         asm volatile("" : "+v"(x2), "+v"(y2), "+v"(z2));
-        fx[0] = (x2 == 0 ? g.nx - 1 : x2 - 1) * EB;
-        fx[1] = x2 * EB;
-        fx[2] = (x2 + 1 == g.nx ? 0 : x2 + 1) * EB;
+        fx[0] = xoff(x2 == 0 ? g.nx - 1 : x2 - 1);
+        fx[1] = xoff(x2);
+        fx[2] = xoff(x2 + 1 == g.nx ? 0 : x2 + 1);
         fy[0] = (y2 == 0 ? g.ny - 1 : y2 - 1) * rowb;
         fy[1] = y2 * rowb;
         fy[2] = (y2 + 1 == g.ny ? 0 : y2 + 1) * rowb;
-        fz[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * planexyb;
-        fz[1] = z2 * planexyb;
-        fz[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * planexyb;
+        fz[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * slabb;
+        fz[1] = z2 * slabb;
+        fz[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * slabb;
     }
 
 #pragma unroll
@@ -308,45 +314,44 @@ StepFn step_fn_sv(int storage, int v, int sw)
 }
 
 // ---------------------------------------------------------------------------
-// Storage location of canonical F_i(x) in a layout: (slot, node).
+// Storage location of canonical F_i(x) in a layout: the slot and the element
+// index in the buffer.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void locate(int layout, int i, uint32_t x, uint32_t y, uint32_t z,
-                                       const Geom& g, int& slot, uint32_t& node)
+__device__ __forceinline__ uint64_t locate(int layout, int i, uint32_t x, uint32_t y, uint32_t z,
+                                           const Geom& g, int& slot)
 {
     const int vx = vel(i, 0), vy = vel(i, 1), vz = vel(i, 2);
-    if (layout == LY_PULL) {
-        // the pull sweep reads F_i(x) from the post-collision buffer at x - v_i
+    if (layout == LY_AA_EVEN) {
         slot = i;
-        node = node_of(wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny), wrap_add(z, -vz, g.nz), g);
-    } else if (layout == LY_AA_EVEN) {
-        slot = i;
-        node = node_of(x, y, z, g);
-    } else {
-        slot = opp(i);
-        node = node_of(wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny), wrap_add(z, -vz, g.nz), g);
+        return pop_index(g, slot, x, y, z);
     }
+    // the pull sweep reads F_i(x) from the post-collision buffer at x - v_i;
+    // the odd AA sweep from the opposite slot there
+    slot = layout == LY_PULL ? i : opp(i);
+    return pop_index(g, slot, wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny),
+                     wrap_add(z, -vz, g.nz));
 }
 
 template <int S>
-__device__ __forceinline__ double load_full(const void* buf, int slot, uint32_t node, int i,
-                                            const Geom& g, const float* inv_scale)
+__device__ __forceinline__ double load_full(const void* buf, uint64_t idx, int slot, int i,
+                                            const float* inv_scale)
 {
     using T = typename Traits<S>::T;
-    const T v = static_cast<const T*>(buf)[slot * g.plane + node];
+    const T v = static_cast<const T*>(buf)[idx];
     if constexpr (S == ST_F64) return (double)v;
     else if constexpr (S == ST_F32) return weight(i) + (double)v;
     else return weight(i) + (double)((float)v * inv_scale[slot]);
 }
 
 template <int S>
-__device__ __forceinline__ void store_full(void* buf, int slot, uint32_t node, int i,
-                                           const Geom& g, const float* scale, double f)
+__device__ __forceinline__ void store_full(void* buf, uint64_t idx, int slot, int i,
+                                           const float* scale, double f)
 {
     using T = typename Traits<S>::T;
     T* b = static_cast<T*>(buf);
-    if constexpr (S == ST_F64) b[slot * g.plane + node] = f;
-    else if constexpr (S == ST_F32) b[slot * g.plane + node] = (float)(f - weight(i));
-    else b[slot * g.plane + node] = (_Float16)((float)(f - weight(i)) * scale[slot]);
+    if constexpr (S == ST_F64) b[idx] = f;
+    else if constexpr (S == ST_F32) b[idx] = (float)(f - weight(i));
+    else b[idx] = (_Float16)((float)(f - weight(i)) * scale[slot]);
 }
 
 // Product-form equilibrium of section II through its one-dimensional
@@ -381,9 +386,8 @@ __global__ void __launch_bounds__(kBlock) k_init_feq(int layout, void* buf, Geom
     for (int i = 0; i < 27; ++i) {
         const double feq = r * ex[i % 3] * ey[(i / 3) % 3] * ez[i / 9];
         int slot;
-        uint32_t node;
-        locate(layout, i, x, y, z, g, slot, node);
-        store_full<S>(buf, slot, node, i, g, sc.scale, feq);
+        const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+        store_full<S>(buf, idx, slot, i, sc.scale, feq);
     }
 }
 
@@ -460,9 +464,8 @@ __global__ void __launch_bounds__(kBlock) k_gather_pop(int layout, const void* b
     node_xyz(n, g, x, y, z);
     for (int i = 0; i < 27; ++i) {
         int slot;
-        uint32_t node;
-        locate(layout, i, x, y, z, g, slot, node);
-        f[i * (size_t)g.nnodes + n] = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+        const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+        f[i * (size_t)g.nnodes + n] = load_full<S>(buf, idx, slot, i, lc.inv_scale);
     }
 }
 
@@ -478,9 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_sample_pop(int layout, const void* b
     node_xyz(n, g, x, y, z);
     for (int i = 0; i < 27; ++i) {
         int slot;
-        uint32_t node;
-        locate(layout, i, x, y, z, g, slot, node);
-        out[27 * (size_t)k + i] = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+        const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+        out[27 * (size_t)k + i] = load_full<S>(buf, idx, slot, i, lc.inv_scale);
     }
 }
 
@@ -494,9 +496,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter_pop(int layout, void* buf, G
     node_xyz(n, g, x, y, z);
     for (int i = 0; i < 27; ++i) {
         int slot;
-        uint32_t node;
-        locate(layout, i, x, y, z, g, slot, node);
-        store_full<S>(buf, slot, node, i, g, sc.scale, f[i * (size_t)g.nnodes + n]);
+        const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+        store_full<S>(buf, idx, slot, i, sc.scale, f[i * (size_t)g.nnodes + n]);
     }
 }
 
@@ -514,9 +515,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf,
     double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < 27; ++i) {
         int slot;
-        uint32_t node;
-        locate(layout, i, x, y, z, g, slot, node);
-        double v = load_full<S>(buf, slot, node, i, g, lc.inv_scale);
+        const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+        double v = load_full<S>(buf, idx, slot, i, lc.inv_scale);
         if constexpr (S != ST_F64) v -= weight(i);
         m += v;
         jx += vel(i, 0) * v;
@@ -730,9 +730,8 @@ __global__ void __launch_bounds__(kBlock) k_gamma_stats(int layout, const void* 
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             int slot;
-            uint32_t node;
-            locate(layout, i, x, y, z, g, slot, node);
-            f[i] = decode<S>(static_cast<const T*>(buf)[slot * g.plane + node], lc.inv_scale[slot]);
+            const uint64_t idx = locate(layout, i, x, y, z, g, slot);
+            f[i] = decode<S>(static_cast<const T*>(buf)[idx], lc.inv_scale[slot]);
         }
         double gam = 0.0;
         collide<S, V, GX>(f, c, &gam);
@@ -897,6 +896,8 @@ __global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
 hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
                        hipStream_t stream)
 {
+    // the AA kernels address populations in planes (see node_update)
+    if (sweep != SW_PULL && !geom_is_planes(p.g)) return hipErrorInvalidValue;
     const StepFn fn = exact_gamma ? step_fn_sv<true>(storage, variant, sweep)
                                   : step_fn_sv<false>(storage, variant, sweep);
     hipLaunchKernelGGL(fn, dim3((p.g.nnodes + kStepBlock - 1) / kStepBlock), dim3(kStepBlock), 0,

@@ -518,7 +518,7 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
     s.g.nnodes = (uint32_t)nnodes;
     s.g.dnx = make_fastdiv(s.g.nx);
     s.g.dny = make_fastdiv(s.g.ny);
-    s.g.plane = nnodes;
+    geom_planes(s.g, 0);   // the pool's sweeps are AA
     s.c = p->defaults;
     const double beta = 1.0 / (6.0 * nu + 1.0);  // nu = (1/3)(1/(2 beta) - 1/2)
     s.c.beta = beta;

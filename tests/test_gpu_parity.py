@@ -89,7 +89,10 @@ def test_taylor_green_32_central_kbc_populations(orc, streaming):
 
 # --------------------------------------------------- ragged / variants ----
 
-RAGGED = [(13, 7, 5), (1, 9, 4), (33, 17, 3), (2, 2, 2), (1, 1, 1), (70, 3, 2)]
+# Pull boxes are x-blocked: (96, 3, 2) in three chunks of 32 nodes, (192, 2, 1)
+# in three chunks of 64, the others in whole rows; AA boxes are in planes.
+RAGGED = [(13, 7, 5), (1, 9, 4), (33, 17, 3), (2, 2, 2), (1, 1, 1), (70, 3, 2), (96, 3, 2),
+          (192, 2, 1)]
 
 
 @pytest.mark.parametrize("shape", RAGGED)
@@ -108,6 +111,27 @@ def test_ragged_boxes_all_variants(orc, shape, streaming):
             err = np.abs(f - F).max()
             assert err <= 1e-13, (shape, streaming, variant, steps, err)
     say(f"ragged {shape} streaming={streaming}: ok")
+
+
+# Bounds: a wrong address gives errors of order 1e-2; these sit a few times
+# above the storage rounding of 7 steps at u up to 0.13.
+@pytest.mark.parametrize("shape", [(128, 4, 3), (96, 4, 3), (40, 3, 4)])
+@pytest.mark.parametrize("dtype,tol", [(kbc.F64, 1e-13), (kbc.F32_DEV, 1e-6),
+                                       (kbc.F32_DEV_X, 3e-8), (kbc.F16_DEV, 1e-4)])
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+def test_layouts_in_every_storage_form(orc, shape, dtype, tol, streaming):
+    """Every storage form in both layouts: pull boxes x-blocked in chunks of
+    64 (nx = 128), 32 (nx = 96) or whole rows (nx = 40), AA boxes in planes;
+    populations after 7 steps of a solenoidal start against the oracle."""
+    u = inputs.hit(shape, 2.0, 0.04, seed=11)
+    nu = 1e-3
+    F = _oracle_run(orc, u, nu, 7)
+    with _box(shape, nu, dtype, streaming=streaming) as b:
+        b.init_velocity(u)
+        b.step(7)
+        err = np.abs(b.populations() - F).max()
+    say(f"layout {shape} dtype={dtype} streaming={streaming}: max|df|={err:.3e}")
+    assert err <= tol
 
 
 @pytest.mark.parametrize("gamma_kind", ["lbgk", "rlb", "rlb_central"])
@@ -211,9 +235,10 @@ def test_diagnostics_match_oracle(orc):
     assert w == pytest.approx(orc.enstrophy(u_o), rel=1e-12)
 
 
-def test_sample_populations_matches_full_copy():
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+def test_sample_populations_matches_full_copy(streaming):
     u = inputs.hit((10, 9, 8), 2.0, 0.04, seed=8)
-    with _box((10, 9, 8), 1e-3, streaming=kbc.AA) as b:
+    with _box((10, 9, 8), 1e-3, streaming=streaming) as b:
         b.init_velocity(u)
         b.step(3)
         f = b.populations().reshape(27, -1)
