@@ -143,7 +143,8 @@ void choose_scales(kbc_handle h, const unsigned* max_bits)
         std::memcpy(&m1, &max_bits[26 - i], sizeof(float));
         double m = std::max<double>(m0, m1);
         m = std::max(m, 1e-4 * weight(i));
-        const int e = (int)std::floor(std::log2(4096.0 / m));
+        // within the int8 range, and defined for a non-finite maximum
+        const int e = (int)std::min(126.0, std::max(-126.0, std::floor(std::log2(4096.0 / m))));
         h->scale[i] = std::ldexp(1.0f, e);
         h->inv_scale[i] = std::ldexp(1.0f, -e);
         h->scale_exp[i] = (int8_t)e;

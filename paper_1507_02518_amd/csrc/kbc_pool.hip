@@ -558,7 +558,8 @@ int kbc_pool_admit(kbc_pool_handle p, const int64_t shape[3], double nu, const d
             std::memcpy(&m1, &mb[26 - i], sizeof(float));
             double m = std::max<double>(m0, m1);
             m = std::max(m, 1e-4 * weight(i));
-            const int ex = (int)std::floor(std::log2(4096.0 / m));
+            // within the int8 range, and defined for a non-finite maximum
+            const int ex = (int)std::min(126.0, std::max(-126.0, std::floor(std::log2(4096.0 / m))));
             s.scale[i] = std::ldexp(1.0f, ex);
             s.inv_scale[i] = std::ldexp(1.0f, -ex);
             s.scale_exp[i] = (int8_t)ex;
