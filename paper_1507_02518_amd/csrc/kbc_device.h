@@ -307,6 +307,35 @@ __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
     ie[0] = e[1] * e[2] * ip;
 }
 
+// ln(1 + x).  Near zero, where the arguments of the exact stabilizer lie in
+// all but strongly non-equilibrium states, the Taylor series
+// x (1 - x/2 + x^2/3 - ... - x^13/14) in Horner form: for |x| < 1/16 the
+// first omitted term is below 2^-56 |x|, so the sum is as accurate as the
+// library function (a few ulp).  Elsewhere the library log1p.
+__host__ __device__ __forceinline__ double log1p_(double x)
+{
+    if (fabs(x) < 0.0625) {
+        double p = -1.0 / 14.0;
+#pragma unroll
+        for (int k = 12; k >= 0; --k) p = fma(p, x, (k % 2 ? -1.0 : 1.0) / (k + 1));
+        return x * p;
+    }
+    return log1p(x);
+}
+
+// 1/x from the hardware estimate refined by two Newton steps (to about one
+// ulp; x is a positive normal number here), in place of an IEEE division.
+__host__ __device__ __forceinline__ double rcp_refined_(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
+
 // Exact stabilizer (section IV, Eq. result1): the root in gamma of
 //   G(gamma) = sum_i dh_i ln(1 + ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / f^eq_i),
 // whose logarithm arguments are f'_i / f^eq_i.  On the interval where all of
@@ -317,8 +346,11 @@ __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
 // dg of gamma moves f'_i by beta dg dh_i, so the iteration stops once the
 // last correction moves no population by more than 1e-16 f^eq_i: further
 // digits of gamma cannot change the result, and where dh << ds they are not
-// determined by G to begin with.  Returns false, leaving gamma to the
-// caller, when no bracket exists.
+// determined by G to begin with.  Two Newton steps in a row give the rate of
+// the quadratic convergence (e_{n+1} ~ e_n^2 |s_n| / s_{n-1}^2), and when the
+// correction that would follow the current one is already below that bound
+// the iteration stops without evaluating G again.  Returns false, leaving
+// gamma to the caller, when no bracket exists.
 template <typename DsFn, typename FneqFn, typename IfeqFn>
 __host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, IfeqFn ifeq_of,
                                                  double beta, double g0, double& gamma)
@@ -341,6 +373,7 @@ __host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, Ife
     if (!(lo < hi) || !(lo > -inf) || !(hi < inf)) return false;
     double g = (g0 > lo && g0 < hi) ? g0 : 0.5 * (lo + hi);
     const double dg_tol = 1e-16 / (beta * hmax);
+    double prev = 0.0;   // size of the last Newton step (0: none yet)
     for (int it = 0; it < 80; ++it) {
         double G = 0.0, D = 0.0;
 #pragma unroll
@@ -348,18 +381,26 @@ __host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, Ife
             const double ds = (double)ds_of(i), dh = (double)fneq_of(i) - ds;
             const double w = (double)ifeq_of(i);
             const double x = ((1.0 - beta * g) * dh - a * ds) * w;
-            G += dh * log1p(x);
-            D += dh * dh * w / (1.0 + x);
+            G += dh * log1p_(x);
+            D += dh * dh * w * rcp_refined_(1.0 + x);
         }
         const double step = G / (beta * D);      // Newton step, G' = -beta D
-        if (fabs(step) <= dg_tol) {              // converged (also when the step
-            g += step;                           // is below one ulp of g)
+        const double as = fabs(step);
+        if (as <= dg_tol ||                      // converged (also when the step
+            (prev > 0.0 && as < prev &&          // is below one ulp of g), or
+             as * as * as <= dg_tol * prev * prev)) {   // the next one would be
+            g += step;
             break;
         }
         if (G > 0.0) lo = g;
         else hi = g;
         double gn = g + step;
-        if (!(gn > lo && gn < hi)) gn = 0.5 * (lo + hi);
+        if (!(gn > lo && gn < hi)) {
+            gn = 0.5 * (lo + hi);
+            prev = 0.0;
+        } else {
+            prev = as;
+        }
         g = gn;
     }
     gamma = g;
