@@ -148,19 +148,24 @@ struct PoolBox {
     int8_t scale_exp[28]; // FP16 storage: stored = (f - W) * 2^scale_exp[i]
 };
 
+// One launch group of a batch: boxes[first .. first + n_active) of the
+// batch's box table, all at the same parity, sorted by tile0 (tiles are
+// numbered from 0 within the group).
 struct PoolMeta {
-    uint32_t n_active;    // boxes in the table, sorted by tile0
-    uint32_t n_tiles;     // total tiles
+    uint32_t first;       // index of the group's first box in the table
+    uint32_t n_active;    // boxes in the group
+    uint32_t n_tiles;     // tiles in the group
     uint32_t block;       // threads per block
     uint32_t sub;         // block-sized sub-tiles per tile
 };
 
 constexpr int kPoolMaxBlock = 512;
 
-// Step k (0-based) of a batch for one parity group: every box of the table
+// Step k (0-based) of a batch for one launch group: every box of the group
 // with k < steps applies the AA sweep `sweep` (SW_AA_EVEN or SW_AA_ODD).
 // Persistent grid-stride loop over the group's tiles; block <= 512.
-// tstart[b] = boxes[b].tile0, a compact copy for the tile -> box search.
+// boxes and tstart are the whole table (tstart[b] = boxes[b].tile0, a
+// compact copy for the tile -> box search); meta is the group's entry.
 hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
                             const uint32_t* tstart, const PoolMeta* meta, int k, int block,
                             int grid, hipStream_t stream);

@@ -194,7 +194,7 @@ k_step(StepParams p)
 
 typedef __attribute__((address_space(1))) char gchar;
 
-// Batched step over one parity group of a pool's boxes (AA sweep SW, in
+// Batched step over one launch group of a pool's boxes (AA sweep SW, in
 // place).  A tile is `sub` consecutive block-sized runs of one box's nodes.
 // Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; a tile
 // belongs to the last box whose first tile is not after it (binary search
@@ -202,11 +202,13 @@ typedef __attribute__((address_space(1))) char gchar;
 // each node is updated by exactly one thread, so a box evolves exactly as it
 // would alone.
 template <int S, int V, int SW>
-__global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ boxes,
-                                                             const uint32_t* __restrict__ tstart,
+__global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ table,
+                                                             const uint32_t* __restrict__ ttable,
                                                              const PoolMeta* __restrict__ meta,
                                                              int k)
 {
+    const PoolBox* __restrict__ boxes = table + meta->first;
+    const uint32_t* __restrict__ tstart = ttable + meta->first;
     const uint32_t n_tiles = meta->n_tiles;
     const uint32_t n_active = meta->n_active;
     const uint32_t block = meta->block;

@@ -86,6 +86,38 @@ def test_each_box_is_identical_alone_and_in_the_mix(dtype):
     say(f"alone vs mix dtype={dtype}: bitwise equal")
 
 
+def test_launch_groups_keep_each_box_identical():
+    """Boxes whose populations together exceed the last-level-cache target of
+    a launch group (216 MiB) run in several groups, each taking all its steps
+    of a batch before the next; with two parities and boxes of different
+    sizes every box still equals its own solo run bit for bit."""
+    dtype = kbc.F64
+    specs = [((64, 64, 64), 4e-4, 23), ((64, 64, 64), 1e-3, 17), ((60, 64, 64), 2e-4, 20),
+             ((56, 56, 64), 3e-3, 13), ((40, 40, 40), 6e-4, 29), ((48, 48, 48), 5e-4, 21),
+             ((64, 64, 48), 7e-4, 15), ((32, 32, 32), 2e-3, 19)]
+    fields = [inputs.hit(sh, 3.0, 0.04, seed=10 + i) for i, (sh, _, _) in enumerate(specs)]
+    first = sum(_pop_bytes(sh, dtype) for sh, _, _ in specs[:6])
+    assert first > 216 << 20
+    budget = sum(_pop_bytes(sh, dtype) for sh, _, _ in specs) + (16 << 20)
+    got = {}
+    with kbc.Pool(budget, dtype, max_slots=8) as pool:
+        slot = {i: pool.admit(fields[i], nu, st) for i, (_, nu, st) in enumerate(specs[:6])}
+        pool.advance(3)
+        for i in (6, 7):
+            slot[i] = pool.admit(fields[i], specs[i][1], specs[i][2])
+        for g in (4, 5, 8, 8, 8):
+            pool.advance(g)
+        pool.sync()
+        for i, (sh, _, _) in enumerate(specs):
+            assert pool.poll(slot[i]) == 0
+            got[i] = pool.result(slot[i], sh)
+    for i, (sh, nu, steps) in enumerate(specs):
+        k, w, rho, u = _alone(sh, nu, fields[i], steps, dtype)
+        assert got[i][0] == k and got[i][1] == w, (i, got[i][:2], (k, w))
+        assert np.array_equal(got[i][2], rho) and np.array_equal(got[i][3], u), i
+    say("launch groups: every box bitwise equal to its solo run")
+
+
 def test_budget_and_slots_bound_admission():
     s = (16, 16, 16)
     u = inputs.taylor_green(s, 0.04)
