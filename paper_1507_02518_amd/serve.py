@@ -115,20 +115,25 @@ def _percentiles(lat):
 
 
 def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=1024,
-                tune_cache=None, log=None, policy="srpt", min_nodes=32 << 20):
+                tune_cache=None, log=None, policy="srpt", min_nodes=8 << 20, age_weight=0.0):
     """Continuous batching over wall-clock arrivals.
 
     policy "all": every resident box advances in every batch (processor
     sharing).  policy "srpt": each batch advances the resident boxes with the
     least remaining work (nodes x steps left) first, adding boxes until the
     batch holds at least `min_nodes` nodes, enough to fill the GPU; the
-    others wait, which lets short requests overtake long ones.
+    others wait, which lets short requests overtake long ones.  With
+    age_weight w > 0 a box's remaining work is reduced by w x (its waiting
+    time) x (the pool's measured rate), so a long request that has waited
+    long enough goes ahead of newly arrived short ones (w -> infinity tends
+    to first-come first-served).
     """
     pending = list(trace)
     active = {}
     left = {}
     done = {}
     results = {}
+    work_done = 0
     with kbc.Pool(budget, dtype, max_slots=max_slots, tune_cache=tune_cache) as pool:
         t0 = time.perf_counter()
         while pending or active:
@@ -151,7 +156,10 @@ def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=10
                 continue
             runnable = [sl for sl in active if left[sl] > 0]
             if policy == "srpt":
-                runnable.sort(key=lambda sl: active[sl].nodes * left[sl])
+                # node-steps per second so far (a typical rate before any work)
+                rate = max(work_done / now, 1e9) if work_done > 0 and now > 0 else 2e10
+                runnable.sort(key=lambda sl: active[sl].nodes * left[sl]
+                              - age_weight * (now - active[sl].arrival) * rate)
                 chosen, nodes = [], 0
                 for sl in runnable:
                     chosen.append(sl)
@@ -163,6 +171,7 @@ def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=10
             if chosen:
                 pool.advance(g, chosen)
                 for sl in chosen:
+                    work_done += active[sl].nodes * min(g, left[sl])
                     left[sl] -= min(g, left[sl])
             # collect finished boxes
             finished = 0
