@@ -217,9 +217,11 @@ int kbc_stream(kbc_handle h, void** stream);
  * shape, its own viscosity and step count) takes 27 * N * bytes-per-
  * population of it and is updated in place with the AA pattern.  One
  * kbc_pool_advance(g) enqueues up to g steps for every unfinished box at once
- * (two launches per step, one per AA parity group, replayed from a captured
- * hipGraph), so boxes admitted while others run share the GPU from their
- * first step on.  Each box evolves exactly as the same box alone (same
+ * (replayed from a captured hipGraph), so boxes admitted while others run
+ * share the GPU from their first step on.  The boxes of a batch are split
+ * into launch groups of one AA parity whose populations fit the GPU's
+ * last-level cache; a group takes all its steps of the batch, one launch per
+ * step, before the next group starts.  Each box evolves exactly as the same box alone (same
  * kernels, same arithmetic), so results do not depend on the mix.  Launch
  * shape (threads per block, blocks: one per tile or a persistent grid,
  * block-sized sub-tiles per tile) comes from an online autotuner.  Batches
@@ -227,7 +229,7 @@ int kbc_stream(kbc_handle h, void** stream);
  * class time each of 12 candidate shapes twice on real work, and the fastest
  * is kept for that class (and per dtype and variant in the text file
  * tune_cache, which may be NULL).  Batches of a class still being measured
- * by another round run one block per tile, 256 threads. 
+ * by another round run one block per tile, 256 threads.
  * ------------------------------------------------------------------------ */
 typedef struct kbc_pool* kbc_pool_handle;
 
