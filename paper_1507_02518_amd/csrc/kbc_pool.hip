@@ -141,7 +141,10 @@ struct LaunchCfg {
 // little below the 256 MB last-level cache) and the most groups per parity.
 // The ensemble pool step measured 25.7-27.5 GLUPS (FP32) on 180-220 MiB of
 // boxes against 22.9-23.5 on 360 MiB and more.
-constexpr size_t kGroupBytes = 216ull << 20;
+#ifndef KBC_POOL_GROUP_MIB
+#define KBC_POOL_GROUP_MIB 216
+#endif
+constexpr size_t kGroupBytes = (size_t)KBC_POOL_GROUP_MIB << 20;
 constexpr int kMaxGroupsPerParity = 80;
 
 // Blocks of a launch: the persistent grid, or one block per tile rounded up
