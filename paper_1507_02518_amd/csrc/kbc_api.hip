@@ -48,8 +48,9 @@ size_t elem_bytes(int dtype)
 // multiple of 64 MiB and large, the 27 read and 27 write streams of a sweep
 // start at addresses that agree in all the low bits, and on MI355X they then
 // contend for the same HBM channels and banks: a 512^3 box ran 10% (FP64 AA),
-// 2% (FP64 pull) and 21% (FP32 AA) slower than with the planes offset by
-// 4352 bytes (17 x 256).  For smaller planes the same offset cost 5-13%, and
+// 2% (FP64 pull), 21% (FP32 AA) and 11% (FP16 AA, 256 MiB planes) slower
+// than with the planes offset by 4352 bytes (17 x 256).  For smaller planes
+// the same offset cost 4-17% (FP32 AA at 64 MiB, FP64 AA at 128 MiB), and
 // for an FP32 pull sweep at 512 MiB planes 1%, so the gap is applied only
 // where it was measured to help.
 constexpr uint64_t kPlaneGapBytes = 4352;
@@ -58,7 +59,7 @@ uint64_t plane_pad_elems(uint64_t nnodes, size_t elem, int streaming)
 {
     const uint64_t bytes = nnodes * elem;
     const bool aligned = bytes % (64ull << 20) == 0;
-    const uint64_t from = streaming == KBC_AA ? (512ull << 20) : (1024ull << 20);
+    const uint64_t from = streaming == KBC_AA ? (256ull << 20) : (1024ull << 20);
     if (!aligned || bytes < from) return 0;
     return kPlaneGapBytes / elem;
 }
