@@ -8,7 +8,7 @@ import tempfile
 import numpy as np
 import pytest
 
-from paper_1507_02518_amd import inputs, kbc
+from paper_1507_02518_amd import inputs, kbc, serve
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +116,27 @@ def test_launch_groups_keep_each_box_identical():
         assert got[i][0] == k and got[i][1] == w, (i, got[i][:2], (k, w))
         assert np.array_equal(got[i][2], rho) and np.array_equal(got[i][3], u), i
     say("launch groups: every box bitwise equal to its solo run")
+
+
+@pytest.mark.parametrize("policy,min_nodes,age_weight", [("srpt", 1 << 16, 0.0),
+                                                         ("srpt", 1 << 16, 0.3),
+                                                         ("all", 0, 0.0)])
+def test_serving_policies_return_the_loops_results(policy, min_nodes, age_weight):
+    """A short served trace (requests arriving while others run, uneven
+    sizes and step counts) under each scheduling policy: every request
+    finishes and its energy and enstrophy equal, bit for bit, those of the
+    first-come first-served loop of single boxes."""
+    trace = serve.serving_trace(12, rate=4000.0, seed=3, edges=(16, 24, 32),
+                                steps_range=(100, 400), u_rms=0.03, k0=2.0)
+    srv = serve.run_serving(trace, kbc.F32_DEV_X, budget=1 << 30, g=10, max_slots=16,
+                            policy=policy, min_nodes=min_nodes, age_weight=age_weight)
+    seq = serve.run_sequential(trace, kbc.F32_DEV_X)
+    assert sorted(srv["results"]) == [r.rid for r in trace]
+    for r in trace:
+        assert srv["results"][r.rid] == seq["results"][r.rid], r.rid
+    assert all(lat > 0 for lat in srv["latencies"])
+    say(f"serving {policy} (min {min_nodes}, aging {age_weight}): p50 {srv['p50_s']:.3f}s "
+        f"p99 {srv['p99_s']:.3f}s, results equal to the loop")
 
 
 def test_budget_and_slots_bound_admission():
