@@ -140,6 +140,15 @@ int kbc_moments(kbc_handle h, double* rho, double* u);
  * reproducible).  Synchronises.  KBC_EUNSTABLE if the state is not finite. */
 int kbc_energy(kbc_handle h, double* k);
 
+/* Advance n >= 0 steps and return the kinetic energy after each of them:
+ * k[j] = k of F(t0 + j + 1), j = 0 .. n-1, host FP64 array of n values
+ * (NULL allowed when n = 0).  The same reduction as kbc_energy (bitwise equal
+ * to calling kbc_step(h, 1) and kbc_energy after every step), but enqueued
+ * with the steps and copied back once at the end; allocates and frees a
+ * device array of n doubles.  Synchronises.  KBC_EUNSTABLE if the state was
+ * not finite after some step (the steps are taken and k is still written). */
+int kbc_energy_series(kbc_handle h, int64_t n, double* k);
+
 /* Enstrophy Omega = (1/2) < |curl u'|^2 >, u' = u - <u>, derivatives by
  * second-order central differences on the periodic grid (section V.A).
  * FP64, fixed reduction order.  Synchronises. */

@@ -418,6 +418,51 @@ int kbc_energy(kbc_handle h, double* k)
     return KBC_OK;
 }
 
+int kbc_energy_series(kbc_handle h, int64_t n, double* k)
+{
+    if (int r = check_handle(h)) return r;
+    if (n < 0) return fail(KBC_EINVAL, "n must be >= 0");
+    if (n > 0 && !k) return fail(KBC_EINVAL, "k is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state (call kbc_init_velocity)");
+    if (n == 0) return KBC_OK;
+    if (int r = set_device(h)) return r;
+    if (int r = ensure_diag(h, false)) return r;
+    double* d_log = nullptr;
+    KBC_HIP(hipMalloc(&d_log, (size_t)n * sizeof(double)));
+    // the non-finite flag accumulates over the n moment launches
+    hipError_t e = hipMemsetAsync(h->d_flag, 0, sizeof(int), h->stream);
+    int r = e == hipSuccess ? KBC_OK : hip_fail(e, "hipMemsetAsync");
+    for (int64_t j = 0; j < n && r == KBC_OK; ++j) {
+        r = kbc_step(h, 1);
+        if (r != KBC_OK) break;
+        e = launch_moments(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale, nullptr,
+                           h->d_u, h->d_flag, h->stream);
+        if (e == hipSuccess)
+            e = launch_reduce(0, h->g, h->d_u, nullptr, h->d_partial, h->d_sum, h->stream);
+        if (e == hipSuccess)
+            e = launch_reduce(1, h->g, h->d_u, h->d_sum, h->d_partial, h->d_sum + 3, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_log + j, h->d_sum + 3, sizeof(double), hipMemcpyDeviceToDevice,
+                               h->stream);
+        if (e != hipSuccess) r = hip_fail(e, "kbc_energy_series");
+    }
+    int flag = 0;
+    if (r == KBC_OK) {
+        e = hipMemcpyAsync(k, d_log, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) r = hip_fail(e, "kbc_energy_series");
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(d_log);
+    if (r != KBC_OK) return r;
+    const double inv2n = 0.5 / (double)h->g.nnodes;
+    for (int64_t j = 0; j < n; ++j) k[j] *= inv2n;
+    if (flag) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
+    return KBC_OK;
+}
+
 int kbc_enstrophy(kbc_handle h, double* omega)
 {
     if (int r = check_handle(h)) return r;

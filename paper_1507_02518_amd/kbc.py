@@ -102,6 +102,7 @@ def load():
         "kbc_step": (ctypes.c_int, [_H, ctypes.c_int64]),
         "kbc_moments": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p]),
         "kbc_energy": (ctypes.c_int, [_H, _D]),
+        "kbc_energy_series": (ctypes.c_int, [_H, ctypes.c_int64, _D]),
         "kbc_enstrophy": (ctypes.c_int, [_H, _D]),
         "kbc_statistics": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(kbc_stats)]),
         "kbc_gamma_statistics": (ctypes.c_int, [_H, ctypes.c_void_p]),
@@ -210,6 +211,13 @@ def kbc_energy(h: int) -> float:
     k = ctypes.c_double()
     _check(load().kbc_energy(h, ctypes.byref(k)), "kbc_energy")
     return k.value
+
+
+def kbc_energy_series(h: int, n: int) -> np.ndarray:
+    k = np.zeros(max(int(n), 0), dtype=np.float64)
+    _check(load().kbc_energy_series(h, int(n), k.ctypes.data_as(_D) if n > 0 else None),
+           "kbc_energy_series")
+    return k
 
 
 def kbc_enstrophy(h: int) -> float:
@@ -401,6 +409,10 @@ class Box:
 
     def energy(self) -> float:
         return kbc_energy(self.h)
+
+    def energy_series(self, n: int) -> np.ndarray:
+        """Advance n steps; k after each of them."""
+        return kbc_energy_series(self.h, n)
 
     def enstrophy(self) -> float:
         return kbc_enstrophy(self.h)

@@ -111,6 +111,7 @@ def test_null_handles_are_rejected():
     assert lib.kbc_step(None, 1) == kbc.KBC_EINVAL
     k = ctypes.c_double()
     assert lib.kbc_energy(None, ctypes.byref(k)) == kbc.KBC_EINVAL
+    assert lib.kbc_energy_series(None, 1, ctypes.byref(k)) == kbc.KBC_EINVAL
     assert lib.kbc_sync(None) == kbc.KBC_EINVAL
     assert lib.kbc_moments(None, None, None) == kbc.KBC_EINVAL
     assert b"null handle" in lib.kbc_last_error()

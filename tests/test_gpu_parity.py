@@ -69,6 +69,33 @@ def test_taylor_green_32_fp64_energy_series_and_populations(orc, streaming):
 
 
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+def test_energy_series_matches_per_step_energy_and_the_oracle(streaming):
+    """kbc_energy_series on the 32^3 Taylor-Green run: k after each of the
+    100 steps equals, bit for bit, kbc_step(1) + kbc_energy on a twin box,
+    and the oracle's stored series within 1e-12 relative; n = 0 and bad
+    arguments."""
+    ref = np.loadtxt(os.path.join(GOLDEN, "oracle_tg32_energy.txt"))
+    u0 = inputs.taylor_green(32, 0.05)
+    with _box(32, 1e-3, streaming=streaming) as a, _box(32, 1e-3, streaming=streaming) as b:
+        a.init_velocity(u0)
+        b.init_velocity(u0)
+        ks = np.concatenate([a.energy_series(40), a.energy_series(0), a.energy_series(60)])
+        kb = []
+        for _ in range(100):
+            b.step(1)
+            kb.append(b.energy())
+        assert a.t == b.t == 100
+        assert np.array_equal(a.populations(), b.populations())
+        with pytest.raises(kbc.KbcError) as e:
+            kbc.kbc_energy_series(a.h, -1)
+        assert e.value.code == kbc.KBC_EINVAL
+    assert np.array_equal(ks, np.array(kb))
+    rel = np.abs(ks / ref[1:, 1] - 1).max()
+    say(f"energy series streaming={streaming}: max rel dk vs oracle {rel:.3e}")
+    assert rel <= 1e-12
+
+
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
 def test_taylor_green_32_central_kbc_populations(orc, streaming):
     """The central-moment default s = d~+t~+q~ on the 32^3 Taylor-Green case
     (U = 0.05, nu = 0.001), 100 steps: populations element-wise and k(100)
