@@ -109,7 +109,10 @@ void kbc_options_default(kbc_options* opt);
  * (beta = 1/(6 nu + 1) in (0, 1)) and the given storage dtype.  opt may be
  * NULL.  Allocates the device population buffers (two lattices for
  * KBC_PULL, one for KBC_AA); the populations are undefined until
- * kbc_init_velocity or kbc_set_populations.  On success *out owns the box. */
+ * kbc_init_velocity or kbc_set_populations.  On success *out owns the box.
+ * The device layout of the populations is internal (x-blocked for pull boxes
+ * whose lattice spans less than 4 GiB, one plane per direction otherwise)
+ * and never crosses this interface. */
 int kbc_create(const int64_t shape[3], double nu, int32_t dtype,
                const kbc_options* opt, kbc_handle* out);
 
