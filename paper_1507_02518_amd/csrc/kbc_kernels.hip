@@ -903,12 +903,13 @@ hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, co
     if (sweep != SW_PULL && !geom_is_planes(p.g)) return hipErrorInvalidValue;
     const StepFn fn = exact_gamma ? step_fn_sv<true>(storage, variant, sweep)
                                   : step_fn_sv<false>(storage, variant, sweep);
-    // One wavefront per workgroup for the exact stabilizer's pull sweep (one
-    // wave per SIMD: 64-thread workgroups fill the CUs more evenly; at 256^3
-    // 14% faster in FP64 and 5% in FP32-X than 256 threads), kStepBlock
-    // threads otherwise (64 measured within +-2% for the other pull forms,
-    // 5% slower for FP16, and 17-33% slower for the AA sweeps).
-    const uint32_t block = (exact_gamma && sweep == SW_PULL) ? 64u : (uint32_t)kStepBlock;
+    // One wavefront per workgroup for the exact stabilizer (one wave per
+    // SIMD: 64-thread workgroups fill the CUs more evenly; at 256^3 the pull
+    // sweep ran 14% (FP64) and 5% (FP32-X) faster than with 256 threads, the
+    // AA sweeps 12% and 8%), kStepBlock threads otherwise (64 measured within
+    // +-2% for the other pull forms, 5% slower for FP16 pull, and 17-33%
+    // slower for the AA sweeps).
+    const uint32_t block = exact_gamma ? 64u : (uint32_t)kStepBlock;
     hipLaunchKernelGGL(fn, dim3((p.g.nnodes + block - 1) / block), dim3(block), 0, stream, p);
     return hipGetLastError();
 }
