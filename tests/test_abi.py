@@ -131,6 +131,23 @@ def test_fast_division_host_check():
         assert r.returncode == 0, r.stdout + r.stderr
 
 
+def test_population_layouts_host_check():
+    """pop_index over the x-blocked layout and planes (with and without a
+    gap): a bijection onto the allocated extent (injective with a gap),
+    contiguous chunks, slot spans and the chunk sizes chosen."""
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("ROCm clang++ not present")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "lay")
+        subprocess.run([clang, "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__",
+                        "-I/opt/rocm/include", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host", "layout_check.cpp"), "-o", exe],
+                       check=True)
+        r = subprocess.run([exe], capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
+
+
 def test_pool_create_rejects_bad_arguments():
     for budget, dtype, slots in [(1 << 30, 9, 8), (1 << 30, kbc.F32_DEV, 0),
                                  (1024, kbc.F32_DEV, 8), (1 << 30, kbc.F32_DEV, 70000)]:
