@@ -204,10 +204,12 @@ def test_exact_entropic_gamma_matches_oracle(orc, streaming, variant):
 
 # ------------------------------------------------------ state handling ----
 
+@pytest.mark.parametrize("shape", [(16, 12, 10), (96, 5, 4)])
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
 @pytest.mark.parametrize("dtype", [kbc.F64, kbc.F32_DEV, kbc.F32_DEV_X, kbc.F16_DEV])
-def test_checkpoint_restart_is_bitwise(streaming, dtype):
-    shape = (16, 12, 10)
+def test_checkpoint_restart_is_bitwise(streaming, dtype, shape):
+    """get_populations / set_populations round trip, also through pull
+    boxes laid out in chunks of 32 nodes (nx = 96)."""
     u = inputs.hit(shape, 3.0, 0.04, seed=4)
     with _box(shape, 5e-4, dtype, streaming=streaming) as a:
         a.init_velocity(u)
