@@ -399,22 +399,27 @@ def test_full_size_central_kbc_sampled_against_oracle(orc):
     assert err <= 1e-14
 
 
-def test_full_size_conservation_512_fp32_aa():
-    """512^3 in-place AA with FP32 deviation storage: total mass and momentum
-    are conserved to the storage precision over 10 steps."""
+# measured drifts over 10 steps: FP32 1.4e-10 (mass) / 6.9e-13 (momentum),
+# FP16 2.0e-8 / 9.7e-11
+@pytest.mark.parametrize("dtype,tol_m,tol_j", [(kbc.F32_DEV, 1e-6, 1e-7),
+                                               (kbc.F16_DEV, 1e-7, 5e-10)])
+def test_full_size_conservation_512_aa(dtype, tol_m, tol_j):
+    """512^3 in-place AA (the precision workload's box, planes with the gap)
+    with FP32 and FP16 deviation storage: total mass and momentum are
+    conserved to the storage precision over 10 steps."""
     n = 512
     u = inputs.taylor_green(n, 0.05)
-    with _box(n, 2.5e-4, kbc.F32_DEV, streaming=kbc.AA) as b:
+    with _box(n, 2.5e-4, dtype, streaming=kbc.AA) as b:
         b.init_velocity(u)
         rho0, u0 = b.moments()
         m0, j0 = rho0.sum(), (rho0[None] * u0).sum(axis=(1, 2, 3))
         b.step(10)
         rho1, u1 = b.moments()
         m1, j1 = rho1.sum(), (rho1[None] * u1).sum(axis=(1, 2, 3))
-    say(f"512^3 f32 AA: mass drift {abs(m1 - m0) / m0:.3e}, momentum drift "
+    say(f"512^3 dtype={dtype} AA: mass drift {abs(m1 - m0) / m0:.3e}, momentum drift "
         f"{np.abs(j1 - j0).max() / m0:.3e}")
-    assert abs(m1 - m0) / m0 < 1e-6
-    assert np.abs(j1 - j0).max() / m0 < 1e-7
+    assert abs(m1 - m0) / m0 < tol_m
+    assert np.abs(j1 - j0).max() / m0 < tol_j
 
 
 # ------------------------------------------------ deviation storage ----
