@@ -170,4 +170,24 @@ hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* 
                             const uint32_t* tstart, const PoolMeta* meta, int k, int block,
                             int grid, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// Kernel tables.  The step, pool and stabilizer-statistics kernels are
+// instantiated in kbc_step_inst.hip, once per storage form S and stabilizer
+// mode GX (exact root or estimate), so that the eight instances compile in
+// parallel; these functions return the kernel for a variant and sweep.
+// ---------------------------------------------------------------------------
+struct LoadCtx {
+    float inv_scale[27];
+};
+using StepFn = void (*)(StepParams);
+using PoolFn = void (*)(const PoolBox*, const uint32_t*, const PoolMeta*, int);
+using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
+
+template <int S, bool GX>
+StepFn step_kernel(int variant, int sweep);
+template <int S>
+PoolFn pool_kernel(int variant, int sweep);   // estimate gamma only
+template <int S, bool GX>
+GammaFn gamma_kernel(int variant);
+
 }  // namespace kbc

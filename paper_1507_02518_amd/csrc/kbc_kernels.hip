@@ -1,350 +1,17 @@
-// kbc_kernels.hip -- gfx950 kernels of the D3Q27 KBC lattice Boltzmann box:
-// the fused stream+collide step (pull and AA sweeps), initialisation at the
-// product-form equilibrium, layout conversion and FP64 diagnostics.
-//
-// Streaming follows f_i(x + v_i, t+1) = f'_i(x, t) on a periodic box
-// (section I, Eq. Egeneral); the collision is kbc::collide (section IV).
+// kbc_kernels.hip -- gfx950 kernels of the D3Q27 KBC lattice Boltzmann box
+// other than the step itself (kbc_step.h, instantiated in kbc_step_inst.hip):
+// initialisation at the product-form equilibrium, layout conversion, FP64
+// diagnostics, the streaming copy, and the launchers of all of them.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "kbc_device.h"
 #include "kbc_internal.h"
+#include "kbc_step.h"
 
 namespace kbc {
 
 namespace {
-
-constexpr int kBlock = 256;
-
-// Build-time tuning of the step kernel (chosen by measurement).
-#ifndef KBC_STEP_BLOCK
-#define KBC_STEP_BLOCK 256
-#endif
-#ifndef KBC_NT_STORE
-#define KBC_NT_STORE 1
-#endif
-#ifndef KBC_WAVES_PER_EU
-#define KBC_WAVES_PER_EU 0
-#endif
-#ifndef KBC_NT_LOAD
-#define KBC_NT_LOAD 0
-#endif
-constexpr int kStepBlock = KBC_STEP_BLOCK;
-
-template <typename T>
-__device__ __forceinline__ void st_pop(T* p, T v)
-{
-    if constexpr (KBC_NT_STORE && sizeof(T) >= 4) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-__device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t n)
-{
-    // a in [0, n), d in {-1, 0, 1}
-    if (d > 0) return a + 1 == n ? 0u : a + 1;
-    if (d < 0) return a == 0 ? n - 1 : a - 1;
-    return a;
-}
-
-__device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, const Geom& g)
-{
-    return (z * g.ny + y) * g.nx + x;
-}
-
-// One node of one step: 27 gathered loads, the collision, 27 stores.
-//   pull:    read src[i][x - v_i], write dst[i][x]
-//   AA even: read buf[i][x],        write buf[26-i][x]
-//   AA odd:  read buf[26-i][x - v_i], write buf[i][x + v_i]
-// In both AA sweeps a node reads and writes the same 27 locations, so the
-// in-place update is free of races between nodes.
-typedef __attribute__((address_space(1))) char gchar_t;
-
-template <int S, int V, int SW, bool GX = false>
-__device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
-                                            const Coll& c, const int8_t* sexp, uint32_t n)
-{
-    using T = typename Traits<S>::T;
-    using R = typename Traits<S>::R;
-    // Addresses are a per-direction plane base (uniform across the wave, kept
-    // in scalar registers) plus a 32-bit byte offset within the plane; the
-    // host guarantees that a plane is smaller than 4 GiB.
-    constexpr uint32_t EB = sizeof(T);
-    uint32_t x, y, z;
-    node_xyz(n, g, x, y, z);
-    const uint32_t rowb = g.row * EB, slabb = g.slab * EB;
-    // Pull boxes may be x-blocked (see Geom); AA boxes are always laid out
-    // in planes, where the offset of x in its row is x itself.
-    auto xoff = [&](uint32_t xx) -> uint32_t {
-        if constexpr (SW == SW_PULL) return (xx >> g.xshift) * (g.chunk * EB) + (xx & g.xmask) * EB;
-        else return xx * EB;
-    };
-    const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
-    const uint32_t ym = y == 0 ? g.ny - 1 : y - 1, yp = y + 1 == g.ny ? 0 : y + 1;
-    const uint32_t zm = z == 0 ? g.nz - 1 : z - 1, zp = z + 1 == g.nz ? 0 : z + 1;
-    // byte offset of coordinate x - v along each axis, indexed by v + 1
-    const uint32_t bx[3] = {xoff(xp), xoff(x), xoff(xm)};
-    const uint32_t by[3] = {yp * rowb, y * rowb, ym * rowb};
-    const uint32_t bz[3] = {zp * slabb, z * slabb, zm * slabb};
-    const uint32_t nb = SW == SW_PULL ? bz[1] + by[1] + bx[1] : n * EB;
-
-    // Loads and stores go through two pointers, which in the AA sweeps hold
-    // the same buffer; they carry no restrict qualifier, and the order of the
-    // accesses comes from the scheduling barrier below.  (One pointer for
-    // both measured slower: in the even sweep the compiler stops addressing
-    // through scalar plane bases, in the odd FP16 sweep it schedules worse.)
-    const char* src = static_cast<const char*>(srcv);
-    char* dst = static_cast<char*>(dstv);
-    const uint64_t planeb = g.plane * EB;
-    // Where every plane is accessed at the same offset (the loads and stores
-    // of the even AA sweep, the stores of the pull sweep) the compiler would
-    // fold buffer + offset into one 64-bit vector address and add each
-    // plane's distance with 64-bit vector arithmetic, two VALU instructions
-    // per access.  Hiding the plane base (a scalar) keeps the scalar-base +
-    // 32-bit-offset form, as for the shifted accesses.  The base passes
-    // through a global-address-space pointer so that the compiler still
-    // knows the accesses are global rather than flat.
-    auto plane = [&](auto* b, int slot, bool hide) {
-        auto* p = b + slot * planeb;
-        if (hide) {
-            gchar_t* q = (gchar_t*)p;
-            asm volatile("" : "+s"(q));
-            p = (decltype(p))q;
-        }
-        return p;
-    };
-    auto ld = [&](int slot, uint32_t off) -> T {
-        const T* p = reinterpret_cast<const T*>(plane(src, slot, SW == SW_AA_EVEN) + off);
-        if constexpr (KBC_NT_LOAD) return __builtin_nontemporal_load(p);
-        else return *p;
-    };
-    auto st = [&](int slot, uint32_t off, T v) {
-        st_pop(reinterpret_cast<T*>(plane(dst, slot, SW != SW_AA_ODD) + off), v);
-    };
-
-    // FP16 scale exponent of direction i: the host makes it equal for i and
-    // its opposite, so 14 distinct values (scalar registers) serve all 27
-    auto ex = [&](int i) -> int { return sexp[i <= 13 ? i : 26 - i]; };
-
-    R f[27];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
-        if constexpr (SW == SW_PULL) {
-            f[i] = decode_exp<S>(ld(i, bz[az] + by[ay] + bx[ax]), ex(i));
-        } else if constexpr (SW == SW_AA_EVEN) {
-            f[i] = decode_exp<S>(ld(i, nb), ex(i));
-        } else {
-            f[i] = decode_exp<S>(ld(opp(i), bz[az] + by[ay] + bx[ax]), ex(i));
-        }
-    }
-
-    if constexpr (SW != SW_PULL) {
-        // AA sweeps read and write the same 27 locations through src and
-        // dst (one buffer): the instruction scheduler may not move any
-        // instruction across this point, so every load is issued before any
-        // store (checked on the built code by the test suite)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-
-    collide<S, V, GX>(f, c);
-
-    // AA odd sweep: store offsets x + v are formed after the collision, from
-    // the coordinates alone, so they do not occupy registers across it (the
-    // empty asm only hides the coordinates from common-subexpression reuse)
-    uint32_t fx[3] = {0, 0, 0}, fy[3] = {0, 0, 0}, fz[3] = {0, 0, 0};
-    if constexpr (SW == SW_AA_ODD) {
-        uint32_t x2 = x, y2 = y, z2 = z;
-        asm volatile("" : "+v"(x2), "+v"(y2), "+v"(z2));
-        fx[0] = xoff(x2 == 0 ? g.nx - 1 : x2 - 1);
-        fx[1] = xoff(x2);
-        fx[2] = xoff(x2 + 1 == g.nx ? 0 : x2 + 1);
-        fy[0] = (y2 == 0 ? g.ny - 1 : y2 - 1) * rowb;
-        fy[1] = y2 * rowb;
-        fy[2] = (y2 + 1 == g.ny ? 0 : y2 + 1) * rowb;
-        fz[0] = (z2 == 0 ? g.nz - 1 : z2 - 1) * slabb;
-        fz[1] = z2 * slabb;
-        fz[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * slabb;
-    }
-
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
-        if constexpr (SW == SW_PULL) {
-            st(i, nb, encode_exp<S>(f[i], ex(i)));
-        } else if constexpr (SW == SW_AA_EVEN) {
-            st(opp(i), nb, encode_exp<S>(f[i], ex(i)));
-        } else {
-            st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
-        }
-    }
-}
-
-// Fused step of one box: one thread per node, workgroups of up to
-// kStepBlock threads (the launch picks the size).  GX: exact stabilizer.
-template <int S, int V, int SW, bool GX>
-__global__ void __launch_bounds__(kStepBlock)
-#if KBC_WAVES_PER_EU
-__attribute__((amdgpu_waves_per_eu(KBC_WAVES_PER_EU, 8)))
-#endif
-k_step(StepParams p)
-{
-    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.g.nnodes) return;
-    node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
-}
-
-typedef __attribute__((address_space(1))) char gchar;
-
-// Batched step over one launch group of a pool's boxes (AA sweep SW, in
-// place).  A tile is `sub` consecutive block-sized runs of one box's nodes.
-// Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; a tile
-// belongs to the last box whose first tile is not after it (binary search
-// over the compact array of first tiles).  Boxes are disjoint in memory and
-// each node is updated by exactly one thread, so a box evolves exactly as it
-// would alone.
-template <int S, int V, int SW>
-__global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ table,
-                                                             const uint32_t* __restrict__ ttable,
-                                                             const PoolMeta* __restrict__ meta,
-                                                             int k)
-{
-    const PoolBox* __restrict__ boxes = table + meta->first;
-    const uint32_t* __restrict__ tstart = ttable + meta->first;
-    const uint32_t n_tiles = meta->n_tiles;
-    const uint32_t n_active = meta->n_active;
-    const uint32_t block = meta->block;
-    const uint32_t sub = meta->sub;
-#pragma unroll 1
-    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        uint32_t lo = 0, hi = n_active;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (tstart[mid] <= tile) lo = mid;
-            else hi = mid;
-        }
-        const PoolBox& b = boxes[lo];
-        if (k >= b.steps) continue;
-        // FP16: the box's scale exponents, staged in LDS once per tile so the
-        // node update reads them there rather than from the box table
-        __shared__ int8_t s_exp[28];
-        if constexpr (S == ST_F16) {
-            __syncthreads();
-            if (threadIdx.x < 28) s_exp[threadIdx.x] = b.scale_exp[threadIdx.x];
-            __syncthreads();
-        }
-        // the box's constants as values, so the population stores cannot be
-        // taken to alias them
-        const Geom g = b.g;
-        const Coll c = b.c;
-        // the table holds a generic pointer; it addresses global memory, and
-        // saying so lets the compiler use global (not flat) loads and stores
-        gchar* const gbuf = (gchar*)b.buf;
-        const uint32_t first = (tile - tstart[lo]) * sub * block;
-#pragma unroll 1
-        for (uint32_t r = 0; r < sub; ++r) {
-            const uint32_t n = first + r * block + threadIdx.x;
-            if (n < g.nnodes) {
-                // loads and stores see the buffer through two global pointers,
-                // as in the single-box kernel (they are kept apart by the
-                // scheduling barrier in node_update)
-                gchar* sbuf = gbuf;
-                gchar* dbuf = gbuf;
-                asm volatile("" : "+s"(sbuf));
-                asm volatile("" : "+s"(dbuf));
-                node_update<S, V, SW>((void*)sbuf, (void*)dbuf, g, c, s_exp, n);
-            }
-        }
-    }
-}
-
-using PoolFn = void (*)(const PoolBox*, const uint32_t*, const PoolMeta*, int);
-
-template <int S, int V>
-PoolFn pool_fn_sw(int sw)
-{
-    return sw == SW_AA_EVEN ? k_pool_step<S, V, SW_AA_EVEN> : k_pool_step<S, V, SW_AA_ODD>;
-}
-
-template <int S>
-PoolFn pool_fn_v(int v, int sw)
-{
-    switch (v) {
-    case V_D: return pool_fn_sw<S, V_D>(sw);
-    case V_DT: return pool_fn_sw<S, V_DT>(sw);
-    case V_DQ: return pool_fn_sw<S, V_DQ>(sw);
-    case V_CD: return pool_fn_sw<S, V_CD>(sw);
-    case V_CDT: return pool_fn_sw<S, V_CDT>(sw);
-    case V_CDQ: return pool_fn_sw<S, V_CDQ>(sw);
-    case V_CDTQ: return pool_fn_sw<S, V_CDTQ>(sw);
-    default: return pool_fn_sw<S, V_DTQ>(sw);
-    }
-}
-
-using StepFn = void (*)(StepParams);
-
-template <int S, int V, bool GX>
-constexpr StepFn step_fn(int sw)
-{
-    return sw == SW_PULL ? k_step<S, V, SW_PULL, GX>
-                         : (sw == SW_AA_EVEN ? k_step<S, V, SW_AA_EVEN, GX>
-                                             : k_step<S, V, SW_AA_ODD, GX>);
-}
-
-template <int S, bool GX>
-StepFn step_fn_v(int v, int sw)
-{
-    switch (v) {
-    case V_D: return step_fn<S, V_D, GX>(sw);
-    case V_DT: return step_fn<S, V_DT, GX>(sw);
-    case V_DQ: return step_fn<S, V_DQ, GX>(sw);
-    case V_CD: return step_fn<S, V_CD, GX>(sw);
-    case V_CDT: return step_fn<S, V_CDT, GX>(sw);
-    case V_CDQ: return step_fn<S, V_CDQ, GX>(sw);
-    case V_CDTQ: return step_fn<S, V_CDTQ, GX>(sw);
-    default: return step_fn<S, V_DTQ, GX>(sw);
-    }
-}
-
-template <bool GX>
-StepFn step_fn_sv(int storage, int v, int sw)
-{
-    switch (storage) {
-    case ST_F64: return step_fn_v<ST_F64, GX>(v, sw);
-    case ST_F32: return step_fn_v<ST_F32, GX>(v, sw);
-    case ST_F32X: return step_fn_v<ST_F32X, GX>(v, sw);
-    default: return step_fn_v<ST_F16, GX>(v, sw);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Storage location of canonical F_i(x) in a layout: the slot and the element
-// index in the buffer.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t locate(int layout, int i, uint32_t x, uint32_t y, uint32_t z,
-                                           const Geom& g, int& slot)
-{
-    const int vx = vel(i, 0), vy = vel(i, 1), vz = vel(i, 2);
-    if (layout == LY_AA_EVEN) {
-        slot = i;
-        return pop_index(g, slot, x, y, z);
-    }
-    // the pull sweep reads F_i(x) from the post-collision buffer at x - v_i;
-    // the odd AA sweep from the opposite slot there
-    slot = layout == LY_PULL ? i : opp(i);
-    return pop_index(g, slot, wrap_add(x, -vx, g.nx), wrap_add(y, -vy, g.ny),
-                     wrap_add(z, -vz, g.nz));
-}
-
-template <int S>
-__device__ __forceinline__ double load_full(const void* buf, uint64_t idx, int slot, int i,
-                                            const float* inv_scale)
-{
-    using T = typename Traits<S>::T;
-    const T v = static_cast<const T*>(buf)[idx];
-    if constexpr (S == ST_F64) return (double)v;
-    else if constexpr (S == ST_F32) return weight(i) + (double)v;
-    else return weight(i) + (double)((float)v * inv_scale[slot]);
-}
 
 template <int S>
 __device__ __forceinline__ void store_full(void* buf, uint64_t idx, int slot, int i,
@@ -453,10 +120,6 @@ __global__ void __launch_bounds__(kBlock) k_pop_dev_max(Geom g, const double* __
     block_max_27(d, max_bits);
 }
 
-struct LoadCtx {
-    float inv_scale[27];
-};
-
 template <int S>
 __global__ void __launch_bounds__(kBlock) k_gather_pop(int layout, const void* buf, Geom g,
                                                        LoadCtx lc, double* __restrict__ f)
@@ -541,34 +204,6 @@ __global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf,
 // butterfly within the wavefront, fixed order across wavefronts and blocks.
 // ---------------------------------------------------------------------------
 constexpr int kReduceBlocks = 1024;
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <int K>
-__device__ __forceinline__ void block_sum(double (&acc)[K], double* out)
-{
-    __shared__ double red[kBlock / 64][K];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wave][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) s += red[w][k];
-            out[k] = s;
-        }
-}
-
 template <int KIND>
 __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, const double* __restrict__ u,
                                                    const double* __restrict__ mean_sum,
@@ -716,57 +351,6 @@ __global__ void __launch_bounds__(kBlock) k_grad_stats(Geom g, const double* __r
     block_sum<8>(acc, partial + 8 * blockIdx.x);
 }
 
-// Per-block sums of gamma and gamma^2 and the block's min and max of the
-// stabilizer that the next step would use at each node (the collision up to
-// step 6 on the stored state; nothing is written back).
-template <int S, int V, bool GX>
-__global__ void __launch_bounds__(kBlock) k_gamma_stats(int layout, const void* buf, Geom g, Coll c,
-                                                        LoadCtx lc, double* __restrict__ partial)
-{
-    using T = typename Traits<S>::T;
-    using R = typename Traits<S>::R;
-    double sum = 0.0, sum2 = 0.0, lo = __builtin_inf(), hi = -__builtin_inf();
-    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.nnodes; n += gridDim.x * kBlock) {
-        uint32_t x, y, z;
-        node_xyz(n, g, x, y, z);
-        R f[27];
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            int slot;
-            const uint64_t idx = locate(layout, i, x, y, z, g, slot);
-            f[i] = decode<S>(static_cast<const T*>(buf)[idx], lc.inv_scale[slot]);
-        }
-        double gam = 0.0;
-        collide<S, V, GX>(f, c, &gam);
-        sum += gam;
-        sum2 += gam * gam;
-        lo = fmin(lo, gam);
-        hi = fmax(hi, gam);
-    }
-    double acc[2] = {sum, sum2};
-    block_sum<2>(acc, partial + 4 * blockIdx.x);
-    __shared__ double mn[kBlock / 64], mx[kBlock / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = fmin(lo, __shfl_xor(lo, off, 64));
-        hi = fmax(hi, __shfl_xor(hi, off, 64));
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        mn[wave] = lo;
-        mx[wave] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < kBlock / 64; ++w) {
-            lo = fmin(lo, mn[w]);
-            hi = fmax(hi, mx[w]);
-        }
-        // the block sums went to partial[4b], [4b+1]; min and max follow
-        partial[4 * blockIdx.x + 2] = lo;
-        partial[4 * blockIdx.x + 3] = hi;
-    }
-}
 
 __global__ void __launch_bounds__(kBlock) k_gamma_final(const double* __restrict__ partial,
                                                         int count, double* __restrict__ out)
@@ -901,8 +485,13 @@ hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, co
 {
     // the AA kernels address populations in planes (see node_update)
     if (sweep != SW_PULL && !geom_is_planes(p.g)) return hipErrorInvalidValue;
-    const StepFn fn = exact_gamma ? step_fn_sv<true>(storage, variant, sweep)
-                                  : step_fn_sv<false>(storage, variant, sweep);
+    StepFn fn;
+    switch (storage) {
+    case ST_F64: fn = exact_gamma ? step_kernel<ST_F64, true>(variant, sweep) : step_kernel<ST_F64, false>(variant, sweep); break;
+    case ST_F32: fn = exact_gamma ? step_kernel<ST_F32, true>(variant, sweep) : step_kernel<ST_F32, false>(variant, sweep); break;
+    case ST_F32X: fn = exact_gamma ? step_kernel<ST_F32X, true>(variant, sweep) : step_kernel<ST_F32X, false>(variant, sweep); break;
+    default: fn = exact_gamma ? step_kernel<ST_F16, true>(variant, sweep) : step_kernel<ST_F16, false>(variant, sweep); break;
+    }
     // One wavefront per workgroup for the exact stabilizer (one wave per
     // SIMD: 64-thread workgroups fill the CUs more evenly; at 256^3 the pull
     // sweep ran 14% (FP64) and 5% (FP32-X) faster than with 256 threads, the
@@ -922,10 +511,10 @@ hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* 
     if (sweep != SW_AA_EVEN && sweep != SW_AA_ODD) return hipErrorInvalidValue;
     PoolFn fn;
     switch (storage) {
-    case ST_F64: fn = pool_fn_v<ST_F64>(variant, sweep); break;
-    case ST_F32: fn = pool_fn_v<ST_F32>(variant, sweep); break;
-    case ST_F32X: fn = pool_fn_v<ST_F32X>(variant, sweep); break;
-    default: fn = pool_fn_v<ST_F16>(variant, sweep); break;
+    case ST_F64: fn = pool_kernel<ST_F64>(variant, sweep); break;
+    case ST_F32: fn = pool_kernel<ST_F32>(variant, sweep); break;
+    case ST_F32X: fn = pool_kernel<ST_F32X>(variant, sweep); break;
+    default: fn = pool_kernel<ST_F16>(variant, sweep); break;
     }
     hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, boxes, tstart, meta, k);
     return hipGetLastError();
@@ -1057,35 +646,6 @@ hipError_t launch_grad_stats(int order, const Geom& g, const double* u, double* 
     return hipGetLastError();
 }
 
-namespace {
-using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
-
-template <int S, bool GX>
-GammaFn gamma_fn_v(int v)
-{
-    switch (v) {
-    case V_D: return k_gamma_stats<S, V_D, GX>;
-    case V_DT: return k_gamma_stats<S, V_DT, GX>;
-    case V_DQ: return k_gamma_stats<S, V_DQ, GX>;
-    case V_CD: return k_gamma_stats<S, V_CD, GX>;
-    case V_CDT: return k_gamma_stats<S, V_CDT, GX>;
-    case V_CDQ: return k_gamma_stats<S, V_CDQ, GX>;
-    case V_CDTQ: return k_gamma_stats<S, V_CDTQ, GX>;
-    default: return k_gamma_stats<S, V_DTQ, GX>;
-    }
-}
-
-template <bool GX>
-GammaFn gamma_fn(int storage, int v)
-{
-    switch (storage) {
-    case ST_F64: return gamma_fn_v<ST_F64, GX>(v);
-    case ST_F32: return gamma_fn_v<ST_F32, GX>(v);
-    case ST_F32X: return gamma_fn_v<ST_F32X, GX>(v);
-    default: return gamma_fn_v<ST_F16, GX>(v);
-    }
-}
-}  // namespace
 
 hipError_t launch_gamma_stats(int storage, int variant, bool exact_gamma, int layout,
                               const void* buf, const Geom& g, const Coll& c,
@@ -1095,7 +655,13 @@ hipError_t launch_gamma_stats(int storage, int variant, bool exact_gamma, int la
     LoadCtx lc;
     for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
     const unsigned blocks = std::min<unsigned>(kReduceBlocks, grid_for(g.nnodes));
-    const GammaFn fn = exact_gamma ? gamma_fn<true>(storage, variant) : gamma_fn<false>(storage, variant);
+    GammaFn fn;
+    switch (storage) {
+    case ST_F64: fn = exact_gamma ? gamma_kernel<ST_F64, true>(variant) : gamma_kernel<ST_F64, false>(variant); break;
+    case ST_F32: fn = exact_gamma ? gamma_kernel<ST_F32, true>(variant) : gamma_kernel<ST_F32, false>(variant); break;
+    case ST_F32X: fn = exact_gamma ? gamma_kernel<ST_F32X, true>(variant) : gamma_kernel<ST_F32X, false>(variant); break;
+    default: fn = exact_gamma ? gamma_kernel<ST_F16, true>(variant) : gamma_kernel<ST_F16, false>(variant); break;
+    }
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, stream, layout, buf, g, c, lc, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

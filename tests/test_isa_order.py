@@ -18,17 +18,28 @@ HIPCC = "/opt/rocm/bin/hipcc"
 
 @pytest.fixture(scope="module")
 def asm():
+    """gfx950 assembly of every instance of the step kernels (one per storage
+    form and stabilizer mode, compiled in parallel), concatenated."""
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not present")
-    with tempfile.TemporaryDirectory() as d:
-        subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                        "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
-                        os.path.join(CSRC, "kbc_kernels.hip"), "--offload-device-only",
-                        "-save-temps", "-o", os.path.join(d, "k.o")],
-                       check=True, cwd=d, capture_output=True)
-        path = glob.glob(os.path.join(d, "*gfx950*.s"))[0]
-        return open(path).read()
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(sx):
+        s, x = sx
+        with tempfile.TemporaryDirectory() as d:
+            subprocess.run([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+                            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                            f"-DKBC_INST_STORAGE={s}", f"-DKBC_INST_EXACT={x}",
+                            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+                            os.path.join(CSRC, "kbc_step_inst.hip"), "--offload-device-only",
+                            "-save-temps", "-o", os.path.join(d, "k.o")],
+                           check=True, cwd=d, capture_output=True)
+            path = glob.glob(os.path.join(d, "*gfx950*.s"))[0]
+            return open(path).read()
+
+    units = [(s, x) for x in (1, 0) for s in range(4)]
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return "\n".join(ex.map(one, units))
 
 
 def _kernels(asm, pattern):
