@@ -445,66 +445,89 @@ double kbco_gamma_exact(const double feq[27], const double ds[27],
 }
 
 /* ------------------------------------------------------------------------ */
-/* Collision: the seven steps listed at the end of section IV.               */
+/* Collision of section IV: the KBC mirror state inserted in Eq. Egeneral.  */
 /* ------------------------------------------------------------------------ */
+
+/* Conserved fields of f (section I, with Eq. S): rho = sum_i f_i and
+ * rho u = sum_i v_i f_i.  Returns rho. */
+static double conserved_fields(const double f[27], double u[3])
+{
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 27; ++i) {
+        int v[3];
+        kbco_velocity(i, v);
+        rho += f[i];
+        j[0] += v[0] * f[i];
+        j[1] += v[1] * f[i];
+        j[2] += v[2] * f[i];
+    }
+    u[0] = j[0] / rho;
+    u[1] = j[1] / rho;
+    u[2] = j[2] / rho;
+    return rho;
+}
+
+/* Eq. ksh-representation splits every population as f = k + s + h, and
+ * Eq. ksh-mirror uses the same parts evaluated at equilibrium.  The shear
+ * part s is read from table s_parts (natural moments) or from the central
+ * basis, on f and on f^eq separately: ds = s - s^eq.  The kinematic part k
+ * depends only on rho and u, which f and f^eq share, so it cancels and the
+ * higher-order difference is what is left: dh = h - h^eq = f - f^eq - ds. */
+static void part_differences(const double f[27], const double feq[27], int variant,
+                             double ds[27], double dh[27])
+{
+    double s[27], seq[27];
+    s_of(f, variant, s);
+    s_of(feq, variant, seq);
+    for (int i = 0; i < 27; ++i) {
+        ds[i] = s[i] - seq[i];
+        dh[i] = f[i] - feq[i] - ds[i];
+    }
+}
+
+/* The stabilizer gamma of the mirror state.  Eq. result21: the estimate
+ * gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh> in the entropic scalar
+ * product <X|Y> = sum_i X_i Y_i / f_i^eq; or the root of Eq. result1; or a
+ * fixed value.  Where <dh|dh> <= gamma_eps rho (at equilibrium both
+ * products vanish and the estimate is 0/0) gamma is the LBGK value 2. */
+static double stabilizer(const double feq[27], const double ds[27], const double dh[27],
+                         double rho, double beta, int gamma_mode, double gamma_value,
+                         double gamma_eps)
+{
+    if (gamma_mode == KBCO_GAMMA_FIXED) return gamma_value;
+    double sh = 0.0, hh = 0.0;
+    for (int i = 0; i < 27; ++i) {
+        sh += ds[i] * dh[i] / feq[i];
+        hh += dh[i] * dh[i] / feq[i];
+    }
+    if (hh <= gamma_eps * rho) return 2.0;
+    if (gamma_mode == KBCO_GAMMA_EXACT) {
+        const double g = kbco_gamma_exact(feq, ds, dh, beta);
+        return isnan(g) ? 2.0 : g;
+    }
+    return 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh;
+}
+
+/* Eq. Egeneral relaxes f toward the mirror state, f' = f + beta (f^mirr - f).
+ * With the mirror state of Eq. ksh-mirror, f^mirr - f = 2 (s^eq - s) +
+ * gamma (h^eq - h) = -(2 ds + gamma dh), so f' = f - beta (2 ds + gamma dh). */
+static void relax(const double f[27], const double ds[27], const double dh[27], double beta,
+                  double gamma, double P[27])
+{
+    for (int i = 0; i < 27; ++i) P[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
+}
 
 double kbco_collide(const double F[27], double beta, int variant,
                     int gamma_mode, double gamma_value, double gamma_eps,
                     double P[27], double feq_out[27], double ds_out[27],
                     double dh_out[27])
 {
-    /* 1: conserved quantities rho = sum f, rho u = sum v f. */
-    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < 27; ++i) {
-        int v[3];
-        kbco_velocity(i, v);
-        rho += F[i];
-        j[0] += v[0] * F[i];
-        j[1] += v[1] * F[i];
-        j[2] += v[2] * F[i];
-    }
-    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-
-    /* 2: equilibrium f^eq(rho, u). */
-    double feq[27];
-    kbco_feq(rho, u, feq);
-
-    /* 3: s and s^eq, the shear part of f and of f^eq. */
-    double s[27], seq[27];
-    s_of(F, variant, s);
-    s_of(feq, variant, seq);
-
-    /* 4: ds = s - s^eq;  5: dh = f - f^eq - ds. */
-    double ds[27], dh[27];
-    for (int i = 0; i < 27; ++i) {
-        ds[i] = s[i] - seq[i];
-        dh[i] = F[i] - feq[i] - ds[i];
-    }
-
-    /* 6: gamma from the entropic estimate (Eq. result21), with the entropic
-     * scalar product <X|Y> = sum_i X_i Y_i / f_i^eq. */
-    double gamma;
-    if (gamma_mode == KBCO_GAMMA_FIXED) {
-        gamma = gamma_value;
-    } else {
-        double sh = 0.0, hh = 0.0;
-        for (int i = 0; i < 27; ++i) {
-            sh += ds[i] * dh[i] / feq[i];
-            hh += dh[i] * dh[i] / feq[i];
-        }
-        if (hh <= gamma_eps * rho) {
-            gamma = 2.0;            /* <dh|dh> ~ 0: the LBGK value */
-        } else if (gamma_mode == KBCO_GAMMA_EXACT) {
-            gamma = kbco_gamma_exact(feq, ds, dh, beta);
-            if (isnan(gamma)) gamma = 2.0;
-        } else {
-            gamma = 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh;
-        }
-    }
-
-    /* 7: relax f' = f - beta (2 ds + gamma dh). */
-    for (int i = 0; i < 27; ++i) P[i] = F[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
-
+    double u[3], feq[27], ds[27], dh[27];
+    const double rho = conserved_fields(F, u);
+    kbco_feq(rho, u, feq);                              /* Eq. entropic_eq */
+    part_differences(F, feq, variant, ds, dh);
+    const double gamma = stabilizer(feq, ds, dh, rho, beta, gamma_mode, gamma_value, gamma_eps);
+    relax(F, ds, dh, beta, gamma, P);
     if (feq_out) memcpy(feq_out, feq, sizeof feq);
     if (ds_out) memcpy(ds_out, ds, sizeof ds);
     if (dh_out) memcpy(dh_out, dh, sizeof dh);

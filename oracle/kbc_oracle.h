@@ -15,9 +15,10 @@
  *     opposite direction 26-i.  The paper labels velocities only by triads.
  *   - population fields are [27][nz][ny][nx], x fastest, FP64.
  *   - velocity fields are [3][nz][ny][nx].
- *   - the stored state F(t) is the pre-collision field; one step is
- *     collide (the seven-step KBC listing of section IV) followed by
- *     periodic propagation f_i(x+v_i, t+1) = f'_i(x, t) (Eq. Egeneral).
+ *   - the stored state F(t) is the pre-collision field; one step is the
+ *     KBC collision of section IV (the mirror state of Eq. ksh-mirror in
+ *     Eq. Egeneral) followed by periodic propagation
+ *     f_i(x+v_i, t+1) = f'_i(x, t) (Eq. Egeneral).
  *   - variant: 0 -> s=d, 1 -> s=d+t, 2 -> s=d+q, 3 -> s=d+t+q (section IV,
  *     natural moments); 4..7 -> the same four in the central-moment basis,
  *     s = d~, d~+t~, d~+q~, d~+t~+q~ (section IV; appendix).
@@ -79,8 +80,12 @@ void   kbco_central_column(const double u[3], int m, double col[27]);
 /* Shear part s of f for any variant 0..7. */
 void   kbco_s_of(const double f[27], int variant, double s[27]);
 
-/* One node: the seven-step collision listing of section IV.  Every output
- * pointer except P may be NULL.  Returns the gamma used. */
+/* One node: the KBC collision of section IV.  rho and u of F; f^eq (Eq.
+ * entropic_eq); ds = s - s^eq and dh = f - f^eq - ds (Eqs.
+ * ksh-representation, ksh-mirror; table s_parts); gamma (Eq. result21, or
+ * Eq. result1, or fixed); P = F - beta (2 ds + gamma dh) (Eq. Egeneral with
+ * the mirror state of Eq. ksh-mirror).  Every output pointer except P may be
+ * NULL.  Returns the gamma used. */
 double kbco_collide(const double F[27], double beta, int variant,
                     int gamma_mode, double gamma_value, double gamma_eps,
                     double P[27], double feq[27], double ds[27], double dh[27]);
