@@ -128,6 +128,11 @@ def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=10
     long enough goes ahead of newly arrived short ones (w -> infinity tends
     to first-come first-served).
     """
+    elem = 8 if dtype == kbc.F64 else (2 if dtype == kbc.F16_DEV else 4)
+    for r in trace:
+        if 27 * r.nodes * elem > budget:
+            raise ValueError(f"request {r.rid} ({r.shape}) needs {27 * r.nodes * elem} bytes of "
+                             f"populations, more than the HBM budget of {budget} bytes")
     pending = list(trace)
     active = {}
     left = {}
@@ -144,9 +149,13 @@ def run_serving(trace, dtype=kbc.F32_DEV_X, budget=200 << 30, g=25, max_slots=10
                 try:
                     slot = pool.admit(r.u, r.nu, r.steps)
                 except kbc.KbcError as e:
-                    if e.code == kbc.KBC_ECAPACITY:
-                        break
-                    raise
+                    if e.code != kbc.KBC_ECAPACITY:
+                        raise
+                    if not active:
+                        # nothing resident will ever free room for it
+                        raise RuntimeError(f"request {r.rid} ({r.shape}) does not fit the empty "
+                                           f"pool: {e}") from e
+                    break
                 active[slot] = r
                 left[slot] = r.steps
                 pending.pop(0)

@@ -422,6 +422,57 @@ def test_full_size_conservation_512_aa(dtype, tol_m, tol_j):
     assert np.abs(j1 - j0).max() / m0 < tol_j
 
 
+@pytest.fixture(scope="module")
+def hit512():
+    """The 512^3 decaying-turbulence start (k0 = 8, u_rms = 0.04, seed 2)."""
+    say("building the 512^3 field (k0 = 8, u_rms = 0.04, seed 2)")
+    return inputs.hit(512, 8.0, 0.04, seed=2)
+
+
+def _nodes_512(n, count, seed):
+    """Sampled nodes: the first and last node of a direction plane (where the
+    padded planes meet), both ends of the first row, column and slab (where
+    the periodic gathers and the shifted odd-sweep stores wrap), the middle
+    of the box, then random nodes."""
+    fixed = [0, n ** 3 - 1, n - 1, n * (n - 1), n * n - 1, n * n * (n - 1),
+             n * n * (n - 1) + n - 1, n ** 3 // 2 + n // 2]
+    rng = np.random.default_rng(seed)
+    return np.concatenate([fixed, rng.integers(0, n ** 3, size=count - len(fixed))])
+
+
+# Bounds after 3 steps (per population, absolute).  FP64: rounding order
+# only.  The deviation forms round each stored f - W once per step; the
+# largest deviation of the 512^3 start is that of the face populations,
+# |f^eq - W| <= 0.047 at |u_a| <= 0.19.  FP16 keeps 11 significant bits of
+# (f - W) 2^e, with 2^e chosen so the largest deviation maps below 2^12:
+# one rounding is at most 0.047 / 2048 = 2.3e-5, three steps with the
+# collision mixing them stay below 1e-4.  FP32 storage rounds at
+# 0.047 * 2^-24 = 2.8e-9 per step; the FP32 collision adds the cancellation
+# in F - f^eq (the measured 100-step Taylor-Green errors are 1.5e-7 for the
+# FP32 collision and 3.6e-9 with the FP64-formed non-equilibrium), so the
+# 3-step bounds are 1e-7 and 1e-8.
+@pytest.mark.parametrize("dtype,tol", [(kbc.F64, 1e-14), (kbc.F32_DEV, 1e-7),
+                                       (kbc.F32_DEV_X, 1e-8), (kbc.F16_DEV, 1e-4)])
+def test_full_size_512_aa_sampled_against_oracle(orc, hit512, dtype, tol):
+    """512^3 decaying turbulence (k0 = 8, u_rms = 0.04, nu = 2.5e-4, seed 2)
+    in place with the AA pattern on direction planes spaced by the gap, in
+    each storage form: three steps (even, odd, even sweep; the state is then
+    read back through the odd layout), 32 sampled nodes against the
+    oracle's light-cone evolution."""
+    n, steps, nu = 512, 3, 2.5e-4
+    nodes = _nodes_512(n, 32, seed=512)
+    say(f"512^3 AA dtype={dtype}: GPU")
+    with _box(n, nu, dtype, streaming=kbc.AA) as b:
+        b.init_velocity(hit512)
+        b.step(steps)
+        assert b.t == steps
+        got = b.sample(nodes)
+    ref = _lightcone_reference(orc, hit512, nodes, steps, nu, (n, n, n))
+    err = np.abs(got - ref).max()
+    say(f"512^3 AA dtype={dtype}: sampled max|df| {err:.3e} (bound {tol:.0e})")
+    assert err <= tol
+
+
 # ------------------------------------------------ deviation storage ----
 
 # Bounds are about 2-5x the measured errors (FP32 collision on FP32 storage:
@@ -469,3 +520,34 @@ def test_hit128_fp64_series_matches_oracle_over_2000_steps(streaming):
             ew.append(abs(b.enstrophy() / ref[t, 2] - 1))
     say(f"HIT128 streaming={streaming}: max rel dk {max(ek):.3e}, max rel dOmega {max(ew):.3e}")
     assert max(ek) <= 1e-10 and max(ew) <= 1e-10
+
+
+# Errors of a chaotic flow against the oracle's FP64 series: the measured
+# 2000-step maxima are (k, Omega) 2.9e-4 / 2.6e-4 for the FP32 collision,
+# 3.4e-6 / 7.3e-6 with the FP64-formed non-equilibrium, 7.1e-4 / 1.2e-3 for
+# FP16 storage; they move by tens of percent with any change of rounding, so
+# the bounds sit about 3x above them.  Pull and AA apply the same arithmetic
+# and give the same series.
+@pytest.mark.parametrize("dtype,streaming,tol_k,tol_w", [
+    (kbc.F32_DEV, kbc.PULL, 1e-3, 1e-3),
+    (kbc.F32_DEV_X, kbc.PULL, 1.5e-5, 3e-5),
+    (kbc.F32_DEV_X, kbc.AA, 1.5e-5, 3e-5),
+    (kbc.F16_DEV, kbc.AA, 3e-3, 5e-3)])
+def test_hit128_reduced_precision_series_error_against_oracle(dtype, streaming, tol_k, tol_w):
+    """128^3 decaying HIT (k0 = 4, u_rms = 0.04, nu = 5e-4, seed 1), 2000
+    steps in FP32 / FP16 deviation storage: the largest relative error of
+    k(t) and Omega(t), every 10 steps, against the oracle's stored FP64
+    series, within stated bounds."""
+    ref = np.loadtxt(os.path.join(GOLDEN, "oracle_hit128_series.txt"))
+    u = inputs.hit(128, 4.0, 0.04, seed=1)
+    ek, ew = [], []
+    with _box(128, 5e-4, dtype, streaming=streaming) as b:
+        b.init_velocity(u)
+        for t in range(0, 2001, 10):
+            if t:
+                b.step(10)
+            ek.append(abs(b.energy() / ref[t, 1] - 1))
+            ew.append(abs(b.enstrophy() / ref[t, 2] - 1))
+    say(f"HIT128 dtype={dtype} streaming={streaming}: max rel dk {max(ek):.3e}, "
+        f"max rel dOmega {max(ew):.3e} (bounds {tol_k:.1e}, {tol_w:.1e})")
+    assert max(ek) <= tol_k and max(ew) <= tol_w

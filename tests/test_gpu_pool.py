@@ -34,23 +34,45 @@ BOXES = [((13, 9, 7), 3e-4, 7), ((16, 16, 16), 1e-3, 12), ((20, 6, 11), 5e-3, 9)
          ((8, 8, 8), 2e-4, 1)]
 
 
+# Bounds on rho, u (absolute) and k (relative) after at most 12 steps of
+# solenoidal starts with u_rms = 0.03 (|u_a| up to about 0.1), where the
+# largest stored deviation |f - W| is about 0.025.  FP64 differs by rounding
+# order only.  The deviation forms round every stored population once per
+# step, independently: FP32 at up to 0.025 * 2^-24 = 1.5e-9, FP16 (11
+# significant bits of the scaled deviation) at up to 0.025 / 2048 = 1.2e-5.
+# rho and u sum 27 of them per node and step, a random walk over 12 x 27
+# roundings: sqrt(324) x 1.5e-9 = 3e-8 (FP32), sqrt(324) x 1.2e-5 / 4 = 5e-5
+# (FP16, where most deviations are far below the largest); measured 1.1e-8
+# and 5.2e-5.  k, about u^2 with u ~ 0.03, averages the node errors: measured
+# 9.9e-8 and 4.6e-5, bounds 3e-7 and 2e-4.
+@pytest.mark.parametrize("dtype,tol_ru,tol_k", [(kbc.F64, 1e-14, 1e-12),
+                                                (kbc.F32_DEV_X, 3e-8, 3e-7),
+                                                (kbc.F16_DEV, 2e-4, 2e-4)])
 @pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
-def test_pool_boxes_match_oracle(orc, variant):
-    with kbc.Pool(64 << 20, kbc.F64, variant=variant, max_slots=8) as pool:
+def test_pool_boxes_match_oracle(orc, variant, dtype, tol_ru, tol_k):
+    """Four boxes of different shapes, viscosities and step counts advanced
+    together by the pool kernel, in FP64 and in FP32 / FP16 deviation
+    storage: density, velocity and energy of each against the oracle."""
+    with kbc.Pool(64 << 20, dtype, variant=variant, max_slots=8) as pool:
         slots = []
         for i, (shape, nu, steps) in enumerate(BOXES):
-            u = inputs.smooth_random(shape, 0.05, seed=i)
+            # solenoidal: FP16 storage overflows on the acoustic transients
+            # of a start with divergence
+            u = inputs.hit(shape, 2.0, 0.03, seed=i)
             slots.append((pool.admit(u, nu, steps), shape, nu, steps, u))
         for _ in range(4):
             pool.advance(3)
+        worst = [0.0, 0.0]
         for slot, shape, nu, steps, u in slots:
             k, w, rho, ug = pool.result(slot, shape)
             F = orc.run(orc.init_feq(u), orc.beta_from_nu(nu), steps, variant=variant)
             rho_o, u_o = orc.macros(F)
-            assert np.abs(rho - rho_o).max() <= 1e-14
-            assert np.abs(ug - u_o).max() <= 1e-14
-            assert k == pytest.approx(orc.energy(u_o), rel=1e-12)
-    say(f"pool vs oracle ok (variant {variant})")
+            e_ru = max(np.abs(rho - rho_o).max(), np.abs(ug - u_o).max())
+            e_k = abs(k / orc.energy(u_o) - 1)
+            worst = [max(worst[0], e_ru), max(worst[1], e_k)]
+            assert e_ru <= tol_ru and e_k <= tol_k, (shape, e_ru, e_k)
+    say(f"pool vs oracle (variant {variant}, dtype {dtype}): max |d rho|, |d u| {worst[0]:.3e}, "
+        f"max rel dk {worst[1]:.3e}")
 
 
 @pytest.mark.parametrize("dtype", [kbc.F64, kbc.F32_DEV_X, kbc.F16_DEV])

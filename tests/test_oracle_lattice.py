@@ -215,3 +215,28 @@ def test_kida_start_is_solenoidal_and_symmetric():
     assert np.abs(u[1] - np.transpose(u[0], (1, 2, 0))).max() < 1e-16
     assert np.abs(u[2] - np.transpose(u[1], (1, 2, 0))).max() < 1e-16
     assert np.abs(u[0] - np.transpose(u[2], (1, 2, 0))).max() < 1e-16
+
+
+def test_forced_lbgk_blows_up_on_the_under_resolved_start_where_kbc_decays(orc):
+    """The start of the pool's isolation test (16^3 random field, k0 = 2,
+    u_rms = 0.05, nu = 1e-5): with gamma forced to 2 (LBGK) the oracle's
+    energy passes 100 k0 between steps 150 and 175 and the state is no longer
+    finite by step 300, while the entropic stabilizer keeps it finite and
+    decaying (section V: LBGK fails on under-resolved turbulence where KBC
+    stays stable)."""
+    wild = inputs.hit((16, 16, 16), 2.0, 0.05, seed=0)
+    beta = orc.beta_from_nu(1e-5)
+    k0 = orc.energy(orc.macros(orc.init_feq(wild))[1])
+    assert k0 == pytest.approx(1.5 * 0.05 ** 2, rel=1e-12)
+    F = orc.init_feq(wild)
+    first = None
+    for t in range(25, 301, 25):
+        F = orc.run(F, beta, 25, gamma=2.0)
+        k = orc.energy(orc.macros(F)[1]) if np.isfinite(F).all() else np.inf
+        if first is None and not k <= 100 * k0:
+            first = t
+    assert first == 175
+    assert not np.isfinite(F).all()
+    Fk = orc.run(orc.init_feq(wild), beta, 300)
+    assert np.isfinite(Fk).all()
+    assert orc.energy(orc.macros(Fk)[1]) < k0
