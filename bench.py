@@ -12,6 +12,12 @@ oracle); the other storage forms, the s = d variant, the central-moment
 default s = d~+t~+q~ and the exact stabilizer (root of the entropy condition
 at every node) are measured on the same field and listed under "forms".
 
+The 512^3 in-place (AA) run of decaying HIT (k0 = 8, u_rms = 0.04,
+nu = 2.5e-4, seed 2) in FP32 / FP16 deviation storage and FP64 is timed under
+"big_forms"; the batched ensemble (64 boxes) and a served request trace
+(Poisson arrivals, 512 requests) are each compared with a plain loop of
+single boxes on the same inputs.
+
 Prints one JSON line with MLUPS, the roofline of the step kernel (HBM bound,
 algorithmic bytes 2 * 27 * bytes-per-population per node and step, timed with
 HIP events on the stream the kernel runs on), and the CPU oracle timed on a
@@ -37,6 +43,7 @@ URMS = 0.04
 SEED = 0
 METRIC = "MLUPS + HBM-roofline %, D3Q27 KBC 256^3; ensemble p50/p99 vs plain loop"
 COUNTERS = os.path.join(ROOT, "profiles", "step_f64_pull_256_counters.txt")
+BIG_N, BIG_NU, BIG_K0, BIG_SEED = 512, 2.5e-4, 8.0, 2
 CSRC = os.path.join(ROOT, "paper_1507_02518_amd", "csrc")
 
 
@@ -44,8 +51,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# the files that define the step kernel's code (the host API files do not)
-KERNEL_SOURCES = ("kbc_device.h", "kbc_internal.h", "kbc_kernels.hip")
+# the files that define the step kernel's code and launch shape (the host API
+# files do not)
+KERNEL_SOURCES = ("kbc_device.h", "kbc_internal.h", "kbc_step.h", "kbc_step_inst.hip",
+                  "kbc_kernels.hip")
 
 
 def kernel_source_digest() -> str:
@@ -76,11 +85,11 @@ def read_counters():
 
 
 def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, variant=None,
-              gamma=None):
+              gamma=None, n=N, nu=NU):
     # the box enqueues on `stream` (a torch stream of default priority); the
     # events are recorded on the same stream, so they bracket the launches
     variant = kbc.S_DTQ if variant is None else variant
-    with kbc.Box(N, NU, dtype, variant=variant, streaming=streaming, gamma=gamma,
+    with kbc.Box(n, nu, dtype, variant=variant, streaming=streaming, gamma=gamma,
                  stream=stream.cuda_stream) as box:
         kbc.kbc_init_velocity_device(box.h, u_dev.data_ptr(), None)
         box.step(warmup)
@@ -96,8 +105,8 @@ def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, varian
         ms = e0.elapsed_time(e1) / steps
         bpn = box.bytes_per_node_step()
         k = box.energy()
-    mlups = N ** 3 / (ms * 1e-3) / 1e6
-    gbs = bpn * N ** 3 / (ms * 1e-3) / 1e9
+    mlups = n ** 3 / (ms * 1e-3) / 1e6
+    gbs = bpn * n ** 3 / (ms * 1e-3) / 1e9
     return {"ms_per_step": ms, "mlups": mlups, "algorithmic_GBs": gbs,
             "frac_hbm_peak": gbs / PEAK_HBM_GBS, "bytes_per_node_step": bpn,
             "wall_s": wall, "energy_after": k}
@@ -133,15 +142,16 @@ def ensemble_and_serving(kbc, args):
     out = {}
     cache = os.path.join(tempfile.gettempdir(), "kbc_pool_tune.txt")
     if args.ensemble:
-        log("[bench] ensemble: 64 boxes, edges {24..96}, 500 steps, FP32 storage")
-        boxes = serve.ensemble_boxes(64, seed=0)
+        es = args.ensemble_steps
+        log(f"[bench] ensemble: 64 boxes, edges {{24..96}}, {es} steps, FP32 storage")
+        boxes = serve.ensemble_boxes(64, seed=0, steps=es)
         # warm-up, in which the launch-shape tuner measures its candidates
         serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=True, g=10, tune_cache=cache)
         pool = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=True, tune_cache=cache)
         loop = serve.run_ensemble(boxes, kbc.F32_DEV_X, batched=False)
         same = all(pool["results"][i] == loop["results"][i] for i in pool["results"])
         out["ensemble"] = {
-            "boxes": len(boxes), "steps": 500, "storage": "f32dev_x",
+            "boxes": len(boxes), "steps": es, "storage": "f32dev_x",
             "lattice_updates": pool["lattice_updates"],
             "pool": {"wall_s": round(pool["wall_s"], 4), "mlups": round(pool["mlups"], 1),
                      "launch": {"block": pool["launch"]["block"], "grid": pool["launch"]["grid"]}},
@@ -152,35 +162,53 @@ def ensemble_and_serving(kbc, args):
     if args.serve_requests > 0:
         log(f"[bench] serving: {args.serve_requests} requests, Poisson 20/s")
         trace = serve.serving_trace(args.serve_requests, rate=20.0, seed=0)
-        # shortest remaining work first in batches of >= 8M nodes (best
-        # median); the same with aging in batches of >= 4M nodes (a long
-        # request that has waited goes first: tail no longer than the loop's)
-        def lat(r):
-            return {"p50_s": round(r["p50_s"], 3), "p99_s": round(r["p99_s"], 3),
-                    "mlups": round(r["mlups"], 1), "wall_s": round(r["wall_s"], 3)}
+
+        def lat(runs):
+            # one entry per repetition, then the spread over them
+            d = {"p50_s": round(runs[0]["p50_s"], 3), "p99_s": round(runs[0]["p99_s"], 3),
+                 "mlups": round(runs[0]["mlups"], 1), "wall_s": round(runs[0]["wall_s"], 3)}
+            if len(runs) > 1:
+                for key in ("p50_s", "p99_s", "mlups"):
+                    v = [r[key] for r in runs]
+                    d[key + "_runs"] = [round(x, 3) for x in v]
+                    d[key + "_spread"] = round((max(v) - min(v)) / min(v), 4)
+            return d
 
         def say(name, r):
             log(f"[bench]   {name}: p50 {r['p50_s']:.2f}s p99 {r['p99_s']:.2f}s {r['mlups']:.0f} MLUPS")
 
-        srv = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25, tune_cache=cache,
-                                min_nodes=8 << 20)
-        say("pool", srv)
-        aged = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25, tune_cache=cache,
-                                 min_nodes=4 << 20, age_weight=0.3)
-        say("pool aged", aged)
-        seq = serve.run_sequential(trace, kbc.F32_DEV_X)
-        say("loop", seq)
-        same = all(srv["results"][i] == seq["results"][i] and aged["results"][i] == seq["results"][i]
-                   for i in srv["results"])
-
-        out["serving"] = {
-            "requests": len(trace), "rate_per_s": 20.0, "storage": "f32dev_x",
-            "hbm_budget_GB": 200, "lattice_updates": srv["lattice_updates"],
-            "pool": dict(lat(srv), policy="shortest remaining work first, batches >= 8M nodes"),
-            "pool_aged": dict(lat(aged), policy="shortest remaining work first with aging "
-                                                "(weight 0.3), batches >= 4M nodes"),
-            "loop": dict(lat(seq), policy="first come first served, one box at a time"),
-            "results_equal": same}
+        # policies: "aged" shortest remaining work first with aging (weight
+        # 0.3, batches of >= 4M nodes), the default; "srpt" the same without
+        # aging in batches of >= 8M nodes (best median); "loop" first come
+        # first served, one box at a time
+        runs = {}
+        for rep in range(args.serve_reps):
+            for pol in args.serve_policies.split(","):
+                if pol == "aged":
+                    r = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25,
+                                          tune_cache=cache, min_nodes=4 << 20, age_weight=0.3)
+                elif pol == "srpt":
+                    r = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25,
+                                          tune_cache=cache, min_nodes=8 << 20)
+                elif pol == "loop":
+                    r = serve.run_sequential(trace, kbc.F32_DEV_X)
+                else:
+                    raise SystemExit(f"unknown serving policy {pol!r}")
+                say(f"{pol} (run {rep + 1})", r)
+                runs.setdefault(pol, []).append(r)
+        first = next(iter(runs.values()))[0]
+        same = all(rr["results"][i] == first["results"][i]
+                   for rs in runs.values() for rr in rs for i in first["results"])
+        names = {"aged": ("pool_aged", "shortest remaining work first with aging (weight 0.3), "
+                                       "batches >= 4M nodes"),
+                 "srpt": ("pool", "shortest remaining work first, batches >= 8M nodes"),
+                 "loop": ("loop", "first come first served, one box at a time")}
+        out["serving"] = {"requests": len(trace), "rate_per_s": 20.0, "storage": "f32dev_x",
+                          "hbm_budget_GB": 200, "repetitions": args.serve_reps,
+                          "lattice_updates": first["lattice_updates"], "results_equal": same}
+        for pol, rs in runs.items():
+            key, desc = names[pol]
+            out["serving"][key] = dict(lat(rs), policy=desc)
     return out
 
 
@@ -258,15 +286,53 @@ def precision_512(kbc, inputs, log, steps=2000):
         out[name] = {"ms_per_step": ms, "mlups": n ** 3 / (ms * 1e-3) / 1e6,
                      "algorithmic_GBs": bpn * n ** 3 / (ms * 1e-3) / 1e9, "k_final": k,
                      "omega_final": w}
+    # resolution comparison (not parity): the oracle's 128^3 run of the same
+    # flow (nu / 4, steps / 4), shells kappa <= 32
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_resolution128_spectrum.txt")
+    e128 = None
+    if os.path.exists(golden) and steps == 2000:
+        import numpy as np
+        e128 = np.loadtxt(golden)[:, 2]
     for name in out:
         out[name]["rel_err_k_vs_f64"] = abs(out[name]["k_final"] / out["f64_aa"]["k_final"] - 1)
         out[name]["rel_err_omega_vs_f64"] = abs(out[name]["omega_final"] /
                                                 out["f64_aa"]["omega_final"] - 1)
         out[name]["spectrum_err_vs_f64"] = analysis.spectrum_error(spec[name], spec["f64_aa"])
+        if e128 is not None:
+            out[name]["resolution_vs_oracle128_kappa_le_32"] = analysis.spectrum_error(
+                spec[name], e128, kmax=32)
     return out
 
 
-def cpu_baseline(u, steps):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+ONE_CORE_SNIPPET = """
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_1507_02518_amd import inputs
+u = inputs.hit({n}, {k0}, {urms}, seed={seed})
+F = oracle.init_feq(u)
+t0 = time.perf_counter()
+oracle.run(F, oracle.beta_from_nu({nu}), {steps})
+print(time.perf_counter() - t0, oracle.num_threads())
+"""
+
+
+def cpu_baseline(u, steps, one_core_n=128, one_core_steps=1):
+    """The oracle on the host cores: all threads on `steps` steps of the 256^3
+    box, and one thread (a child process with OMP_NUM_THREADS=1) on
+    `one_core_steps` steps of a 128^3 box of the same flow."""
+    import subprocess
+
     import oracle
 
     F = oracle.init_feq(u)
@@ -274,10 +340,66 @@ def cpu_baseline(u, steps):
     t0 = time.perf_counter()
     oracle.run(F, beta, steps)
     dt = time.perf_counter() - t0
+    del F
+    code = ONE_CORE_SNIPPET.format(root=ROOT, n=one_core_n, k0=K0, urms=URMS, seed=SEED, nu=NU,
+                                   steps=one_core_steps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         check=True).stdout.split()
+    dt1, thr1 = float(one[0]), int(one[1])
     return {"value": N ** 3 * steps / dt / 1e6, "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{steps} step(s) of the same 256^3 HIT box, FP64, s=d+t+q, "
-                      f"{dt:.1f} s of CPU time on {oracle.num_threads()} OpenMP threads"}
+                      f"{dt:.1f} s of CPU time on {oracle.num_threads()} OpenMP threads",
+            "one_core": {"value": one_core_n ** 3 * one_core_steps / dt1 / 1e6, "unit": "MLUPS",
+                         "cores": thr1,
+                         "sample": f"{one_core_steps} step(s) of a {one_core_n}^3 box of the "
+                                   f"same flow, {dt1:.1f} s on one thread"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "host_cpus_usable": len(os.sched_getaffinity(0))}
+
+
+FORMS_256 = [  # name, storage, streaming, variant ("exact": the exact stabilizer)
+    ("f64_aa", "F64", "AA", None), ("f32dev_pull", "F32_DEV", "PULL", None),
+    ("f32dev_aa", "F32_DEV", "AA", None), ("f32devx_pull", "F32_DEV_X", "PULL", None),
+    ("f32devx_aa", "F32_DEV_X", "AA", None), ("f16dev_aa", "F16_DEV", "AA", None),
+    ("f16dev_pull", "F16_DEV", "PULL", None), ("f64_pull_s_d", "F64", "PULL", "S_D"),
+    ("f64_pull_central", "F64", "PULL", "S_CDTQ"),
+    ("f32devx_pull_central", "F32_DEV_X", "PULL", "S_CDTQ"),
+    ("f16dev_aa_central", "F16_DEV", "AA", "S_CDTQ"),
+    ("f64_pull_exact_gamma", "F64", "PULL", "exact"),
+    ("f32devx_pull_exact_gamma", "F32_DEV_X", "PULL", "exact")]
+BIG_FORMS = [("f32devx_aa", "F32_DEV_X"), ("f16dev_aa", "F16_DEV"), ("f32dev_aa", "F32_DEV"),
+             ("f64_aa", "F64")]
+
+
+def _select(spec, names):
+    if spec == "all":
+        return list(names)
+    if spec == "none":
+        return []
+    want = spec.split(",")
+    bad = [w for w in want if w not in names]
+    if bad:
+        raise SystemExit(f"unknown form(s) {bad}; choose from {list(names)}")
+    return want
+
+
+def run_forms(kbc, torch, u_dev, table, names, steps, warmup, stream, n, nu):
+    out = {}
+    for name, dt, st, var in table:
+        if name not in names:
+            continue
+        log(f"[bench] {n}^3 {name}")
+        gamma = None
+        if var == "exact":
+            var, gamma = None, "exact"
+        variant = getattr(kbc, var) if var else None
+        r = time_form(kbc, torch, u_dev, getattr(kbc, dt), getattr(kbc, st), steps, warmup,
+                      stream, variant, gamma, n=n, nu=nu)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
+    return out
 
 
 def main():
@@ -287,9 +409,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    help="256^3 forms to time besides the headline: all, none or a list")
+    ap.add_argument("--no-forms", dest="forms", action="store_const", const="none")
+    ap.add_argument("--big-forms", default="f32devx_aa,f16dev_aa,f64_aa",
+                    help="512^3 AA forms (all, none or a list of "
+                         + ",".join(n for n, _ in BIG_FORMS) + ")")
+    ap.add_argument("--big-steps", type=int, default=20)
+    ap.add_argument("--big-warmup", type=int, default=4)
     ap.add_argument("--no-ensemble", dest="ensemble", action="store_false")
-    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-policies", default="aged,loop",
+                    help="comma list of aged, srpt, loop")
+    ap.add_argument("--serve-reps", type=int, default=1)
     ap.add_argument("--precision", action="store_true",
                     help="run the storage-precision study (128^3 and 512^3) instead")
     ap.add_argument("--precision-steps-512", type=int, default=2000)
@@ -298,6 +431,8 @@ def main():
         print(f"bench.py measures one GPU only: the KBC box runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
+    forms_256 = _select(args.forms, [f[0] for f in FORMS_256])
+    forms_512 = _select(args.big_forms, [f[0] for f in BIG_FORMS])
 
     import torch
 
@@ -326,34 +461,23 @@ def main():
     head = time_form(kbc, torch, u_dev, kbc.F64, kbc.PULL, args.steps, args.warmup, stream)
     log(f"[bench]   {head['mlups']:.0f} MLUPS, {head['algorithmic_GBs']:.0f} GB/s")
 
-    forms = {}
-    if not args.no_forms:
-        C = kbc.S_CDTQ
-        for name, dt, st, var in [("f64_aa", kbc.F64, kbc.AA, None),
-                                  ("f32dev_pull", kbc.F32_DEV, kbc.PULL, None),
-                                  ("f32dev_aa", kbc.F32_DEV, kbc.AA, None),
-                                  ("f32devx_pull", kbc.F32_DEV_X, kbc.PULL, None),
-                                  ("f32devx_aa", kbc.F32_DEV_X, kbc.AA, None),
-                                  ("f16dev_aa", kbc.F16_DEV, kbc.AA, None),
-                                  ("f16dev_pull", kbc.F16_DEV, kbc.PULL, None),
-                                  ("f64_pull_s_d", kbc.F64, kbc.PULL, kbc.S_D),
-                                  ("f64_pull_central", kbc.F64, kbc.PULL, C),
-                                  ("f32devx_pull_central", kbc.F32_DEV_X, kbc.PULL, C),
-                                  ("f16dev_aa_central", kbc.F16_DEV, kbc.AA, C),
-                                  ("f64_pull_exact_gamma", kbc.F64, kbc.PULL, "exact"),
-                                  ("f32devx_pull_exact_gamma", kbc.F32_DEV_X, kbc.PULL,
-                                   "exact")]:
-            log(f"[bench] {name}")
-            gamma = None
-            if var == "exact":
-                var, gamma = None, "exact"
-            r = time_form(kbc, torch, u_dev, dt, st, args.steps, args.warmup, stream, var, gamma)
-            forms[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-            log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
+    forms = run_forms(kbc, torch, u_dev, FORMS_256, forms_256, args.steps, args.warmup, stream,
+                      N, NU)
     log("[bench] copy ceiling")
     copy_gbs = copy_ceiling(kbc, torch, stream)
     del u_dev
     torch.cuda.empty_cache()
+
+    big = {}
+    if forms_512:
+        log(f"[bench] building the {BIG_N}^3 HIT field (k0 = {BIG_K0}, seed {BIG_SEED})")
+        ub = torch.from_numpy(inputs.hit(BIG_N, BIG_K0, URMS, seed=BIG_SEED)).cuda()
+        torch.cuda.synchronize()
+        table = [(nm, dt, "AA", None) for nm, dt in BIG_FORMS]
+        big = run_forms(kbc, torch, ub, table, forms_512, args.big_steps, args.big_warmup, stream,
+                        BIG_N, BIG_NU)
+        del ub
+        torch.cuda.empty_cache()
 
     batched = ensemble_and_serving(kbc, args)
 
@@ -373,9 +497,10 @@ def main():
     }
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] CPU oracle sample ({args.cpu_steps} step(s) at 256^3)")
+        log(f"[bench] CPU oracle sample ({args.cpu_steps} step(s) at 256^3, then one thread)")
         cpu = cpu_baseline(u, args.cpu_steps)
-        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads")
+        log(f"[bench]   {cpu['value']:.3f} MLUPS on {cpu['cores']} threads, "
+            f"{cpu['one_core']['value']:.3f} MLUPS on one")
 
     out = {
         "metric": METRIC,
@@ -396,6 +521,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "big_forms": {"workload": f"{BIG_N}^3 decaying HIT, k0={BIG_K0:g}, u_rms={URMS}, "
+                                  f"nu={BIG_NU}, seed {BIG_SEED}, in place (AA), s=d+t+q",
+                      "steps": args.big_steps, "warmup": args.big_warmup, **big} if big else None,
     }
     out.update(batched)
     print(json.dumps(out), flush=True)

@@ -128,8 +128,10 @@ int kbc_init_velocity(kbc_handle h, const double* u, const double* rho);
 /* Same, with u and rho already in device memory (same layouts). */
 int kbc_init_velocity_device(kbc_handle h, const double* u_dev, const double* rho_dev);
 
-/* Enqueue n >= 0 steps (one kernel launch per step) on the box's stream and
- * return; t advances by n. */
+/* Enqueue n >= 0 steps on the box's stream and return; t advances by n.
+ * Each step is one kernel launch; from n >= 16 on, runs of 16 steps are
+ * replayed from a graph the box builds on first use (the same kernels and
+ * arguments, so the same results as 16 single launches). */
 int kbc_step(kbc_handle h, int64_t n);
 
 /* Density and velocity of F(t) (section I: rho = sum_i f_i, rho u =

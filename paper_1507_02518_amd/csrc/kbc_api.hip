@@ -94,6 +94,12 @@ struct kbc_box {
     int* d_flag;
     unsigned* d_max;
     double* d_pop;      // canonical staging [27][N]
+    // kStepGraph consecutive steps as one graph, built on first use, for the
+    // state it starts from (pull: P(t-1) in buf[0]; AA: even t); its kernel
+    // arguments hold the buffers, geometry, constants and FP16 exponents, so
+    // it is dropped whenever the exponents change
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
 };
 
 namespace {
@@ -166,6 +172,103 @@ int compute_moments(kbc_handle h, bool want_rho)
     KBC_HIP(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     KBC_HIP(hipStreamSynchronize(h->stream));
     if (flag) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
+    return KBC_OK;
+}
+
+// Steps per graph of kbc_step (0: every step is its own launch).  A box
+// advanced n >= kStepGraph steps replays the graph floor(n / kStepGraph)
+// times after at most one single step that brings it to the graph's start
+// state; the remainder runs as single launches.  The graph holds the same
+// kernels with the same arguments as the single launches, so the results
+// are the same bits.
+#ifndef KBC_STEP_GRAPH
+#define KBC_STEP_GRAPH 16
+#endif
+constexpr int kStepGraph = KBC_STEP_GRAPH;
+static_assert(kStepGraph % 2 == 0, "a graph must return the box to its start state");
+
+void drop_graph(kbc_handle h)
+{
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+}
+
+bool at_graph_start(const kbc_box* h)
+{
+    return h->streaming == KBC_PULL ? h->cur == 0 : h->t % 2 == 0;
+}
+
+StepParams step_params(const kbc_box* h)
+{
+    StepParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.g = h->g;
+    p.c = h->coll;
+    static_assert(sizeof(p.scale_exp) == sizeof(h->scale_exp), "exponent layout");
+    std::memcpy(p.scale_exp, h->scale_exp, sizeof(p.scale_exp));
+    return p;
+}
+
+// Sweep and buffers of the step taken from pull buffer `cur` or AA time t.
+int step_sweep(const kbc_box* h, int cur, int64_t t, StepParams& p)
+{
+    if (h->streaming == KBC_PULL) {
+        p.src = h->buf[cur];
+        p.dst = h->buf[1 - cur];
+        return SW_PULL;
+    }
+    p.src = h->buf[0];
+    p.dst = h->buf[0];
+    return t % 2 == 0 ? SW_AA_EVEN : SW_AA_ODD;
+}
+
+int build_graph(kbc_handle h)
+{
+    hipGraph_t graph = nullptr;
+    KBC_HIP(hipGraphCreate(&graph, 0));
+    StepParams p = step_params(h);
+    hipGraphNode_t prev = nullptr;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kStepGraph && e == hipSuccess; ++k) {
+        const int sweep = step_sweep(h, k % 2, k, p);
+        StepFn fn;
+        uint32_t grid, block;
+        e = step_launch_shape(h->dtype, h->variant, sweep, h->exact_gamma, h->g, &fn, &grid, &block);
+        if (e != hipSuccess) break;
+        void* args[] = {&p};
+        hipKernelNodeParams np;
+        std::memset(&np, 0, sizeof(np));
+        np.func = reinterpret_cast<void*>(fn);
+        np.gridDim = dim3(grid);
+        np.blockDim = dim3(block);
+        np.sharedMemBytes = 0;
+        np.kernelParams = args;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+        prev = node;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "building the step graph");
+    }
+    h->graph = graph;
+    h->graph_exec = exec;
+    return KBC_OK;
+}
+
+// One step as its own launch.
+int step_once(kbc_handle h)
+{
+    StepParams p = step_params(h);
+    const int sweep = step_sweep(h, h->cur, h->t, p);
+    KBC_HIP(launch_step(h->dtype, h->variant, sweep, h->exact_gamma, p, h->stream));
+    if (h->streaming == KBC_PULL) h->cur = 1 - h->cur;
+    h->t += 1;
     return KBC_OK;
 }
 
@@ -294,6 +397,7 @@ int kbc_destroy(kbc_handle h)
     if (!h) return KBC_OK;
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
     for (void* p : {h->buf[0], h->buf[1], (void*)h->d_u, (void*)h->d_rho, (void*)h->d_partial,
                     (void*)h->d_sum, (void*)h->d_flag, (void*)h->d_max, (void*)h->d_pop})
         if (p) (void)hipFree(p);
@@ -321,6 +425,7 @@ static int init_from_device(kbc_handle h, const double* du, const double* drho)
         KBC_HIP(hipStreamSynchronize(h->stream));
         choose_scales(h, mb);
     }
+    drop_graph(h);
     h->t = 0;
     h->cur = 0;
     KBC_HIP(launch_init_feq(h->dtype, layout_now(h), state_buf(h), h->g, h->scale, du, drho,
@@ -358,27 +463,21 @@ int kbc_step(kbc_handle h, int64_t n)
     if (!h->initialised) return fail(KBC_ESTATE, "box has no state (call kbc_init_velocity)");
     if (n == 0) return KBC_OK;
     if (int r = set_device(h)) return r;
-    StepParams p;
-    std::memset(&p, 0, sizeof(p));
-    p.g = h->g;
-    p.c = h->coll;
-    static_assert(sizeof(p.scale_exp) == sizeof(h->scale_exp), "exponent layout");
-    std::memcpy(p.scale_exp, h->scale_exp, sizeof(p.scale_exp));
-    for (int64_t k = 0; k < n; ++k) {
-        int sweep;
-        if (h->streaming == KBC_PULL) {
-            sweep = SW_PULL;
-            p.src = h->buf[h->cur];
-            p.dst = h->buf[1 - h->cur];
-        } else {
-            sweep = (h->t % 2 == 0) ? SW_AA_EVEN : SW_AA_ODD;
-            p.src = h->buf[0];
-            p.dst = h->buf[0];
+    int64_t left = n;
+    if (kStepGraph > 0 && n >= kStepGraph) {
+        if (!at_graph_start(h)) {
+            if (int r = step_once(h)) return r;
+            --left;
         }
-        KBC_HIP(launch_step(h->dtype, h->variant, sweep, h->exact_gamma, p, h->stream));
-        if (h->streaming == KBC_PULL) h->cur = 1 - h->cur;
-        h->t += 1;
+        if (left >= kStepGraph && !h->graph_exec)
+            if (int r = build_graph(h)) return r;
+        for (; left >= kStepGraph; left -= kStepGraph) {
+            KBC_HIP(hipGraphLaunch(h->graph_exec, h->stream));
+            h->t += kStepGraph;   // and the pull buffers are back where they were
+        }
     }
+    for (; left > 0; --left)
+        if (int r = step_once(h)) return r;
     return KBC_OK;
 }
 
@@ -623,6 +722,7 @@ int kbc_set_populations(kbc_handle h, const double* f, int64_t t)
         KBC_HIP(hipStreamSynchronize(h->stream));
         choose_scales(h, mb);
     }
+    drop_graph(h);
     h->t = t;
     h->cur = 0;
     KBC_HIP(launch_scatter_pop(h->dtype, layout_now(h), state_buf(h), h->g, h->scale, h->d_pop,

@@ -195,18 +195,20 @@ __device__ __forceinline__ typename Traits<S>::T encode(typename Traits<S>::R v,
 
 // ---------------------------------------------------------------------------
 // Collision of one node, in place on f[27] (f_i for F64, g_i = f_i - W_i for
-// the deviation forms).  Steps follow the listing at the end of section IV:
-//  1. rho, u from a separable 3x3x3 moment transform of f;
-//  2. f^eq from its one-dimensional marginals: with S = sqrt(1+3u^2) the
-//     product-form factors of section II reduce to e_0 = (4 - 2S)/3,
+// the deviation forms): the KBC mirror state of section IV inserted in
+// Eq. Egeneral, f' = f - beta (2 ds + gamma dh).
+//   - rho and u from a separable 3x3x3 moment transform of f;
+//   - f^eq (Eq. entropic_eq) from its one-dimensional marginals: with
+//     S = sqrt(1+3u^2) the product-form factors reduce to e_0 = (4 - 2S)/3,
 //     e_{+-1} = ((2S - 1)/3 +- u)/2 per axis, f_i^eq = rho e(vx) e(vy) e(vz);
-//  3-4. ds from the differences of the 13 second- and third-order natural
-//     moments of f and f^eq (table s_parts), or, for the central variants,
-//     from the central moments of those differences (appendix);
-//  5. dh = f - f^eq - ds;
-//  6. gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh>, 1/f^eq_i separable;
-//     gamma = 2 where <dh|dh> <= gamma_eps * rho (0/0 at equilibrium);
-//  7. f' = f - beta (2 ds + gamma dh).
+//   - ds = s - s^eq from the differences of the 13 second- and third-order
+//     natural moments of f and f^eq (table s_parts), or, for the central
+//     variants, from the central moments of those differences (appendix);
+//   - dh = f - f^eq - ds (Eq. ksh-representation: the kinematic part
+//     depends only on rho and u, so it cancels);
+//   - gamma = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> (Eq. result21),
+//     1/f^eq_i separable; gamma = 2 where <dh|dh> <= gamma_eps * rho (0/0
+//     at equilibrium).
 // ---------------------------------------------------------------------------
 
 // Separable moment transform along x, then y, then z: for each line of three
@@ -307,20 +309,24 @@ __host__ __device__ __forceinline__ void recip3(const R (&e)[3], R (&ie)[3])
     ie[0] = e[1] * e[2] * ip;
 }
 
-// ln(1 + x).  Near zero, where the arguments of the exact stabilizer lie in
-// all but strongly non-equilibrium states, the Taylor series
-// x (1 - x/2 + x^2/3 - ... - x^13/14) in Horner form: for |x| < 1/16 the
+// ln(1 + x) near zero, where the arguments of the exact stabilizer lie in all
+// but strongly non-equilibrium states: the Taylor series
+// x (1 - x/2 + x^2/3 - ... - x^13/14) in Horner form.  For |x| < 1/16 the
 // first omitted term is below 2^-56 |x|, so the sum is as accurate as the
-// library function (a few ulp).  Elsewhere the library log1p.
+// library function (a few ulp); log1p_ takes the library log1p elsewhere.
+__host__ __device__ __forceinline__ double log1p_series(double x)
+{
+    double p = -1.0 / 14.0;
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma(p, x, (k % 2 ? -1.0 : 1.0) / (k + 1));
+    return x * p;
+}
+
+__host__ __device__ __forceinline__ bool log1p_series_ok(double x) { return fabs(x) < 0.0625; }
+
 __host__ __device__ __forceinline__ double log1p_(double x)
 {
-    if (fabs(x) < 0.0625) {
-        double p = -1.0 / 14.0;
-#pragma unroll
-        for (int k = 12; k >= 0; --k) p = fma(p, x, (k % 2 ? -1.0 : 1.0) / (k + 1));
-        return x * p;
-    }
-    return log1p(x);
+    return log1p_series_ok(x) ? log1p_series(x) : log1p(x);
 }
 
 // 1/x from the hardware estimate refined by two Newton steps (to about one
@@ -337,54 +343,71 @@ __host__ __device__ __forceinline__ double rcp_refined_(double x)
 }
 
 // Exact stabilizer (section IV, Eq. result1): the root in gamma of
-//   G(gamma) = sum_i dh_i ln(1 + ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / f^eq_i),
-// whose logarithm arguments are f'_i / f^eq_i.  On the interval where all of
-// them are positive G falls strictly (G' = -beta sum_i dh_i^2 / (f^eq_i arg_i)),
-// so the root there is unique.  Newton's method from the estimate g0, each
-// iterate kept inside a bracket that shrinks with the sign of G (a step that
-// leaves it is replaced by bisection); FP64 for every storage form.  A change
-// dg of gamma moves f'_i by beta dg dh_i, so the iteration stops once the
-// last correction moves no population by more than 1e-16 f^eq_i: further
-// digits of gamma cannot change the result, and where dh << ds they are not
-// determined by G to begin with.  Two Newton steps in a row give the rate of
-// the quadratic convergence (e_{n+1} ~ e_n^2 |s_n| / s_{n-1}^2), and when the
-// correction that would follow the current one is already below that bound
-// the iteration stops without evaluating G again.  Returns false, leaving
-// gamma to the caller, when no bracket exists.
-template <typename DsFn, typename FneqFn, typename IfeqFn>
-__host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, IfeqFn ifeq_of,
-                                                 double beta, double g0, double& gamma)
+//   G(gamma) = sum_i dh_i ln(1 + x_i),  x_i = ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / f^eq_i,
+// where 1 + x_i = f'_i / f^eq_i.  The caller passes, per population, dh_i,
+// hw_i = dh_i / f^eq_i and cc_i = (dh_i - (2 beta - 1) ds_i) / f^eq_i, so that
+// x_i = cc_i - beta gamma hw_i.  With r_i = 1 / (1 + x_i),
+//   G'  = -beta   sum_i dh_i hw_i r_i           = -beta D1,
+//   G'' = -beta^2 sum_i dh_i (hw_i r_i)^2       = -beta^2 D2.
+// On the interval where all 1 + x_i are positive G falls strictly (D1 > 0),
+// so the root there is unique.  Halley's iteration from the estimate g0,
+// step = 2 G D1 / (beta (2 D1^2 + G D2)) (Newton's G / (beta D1) where
+// |G D2| > D1^2), each iterate kept inside a bracket that shrinks with the
+// sign of G (a step that leaves it is replaced by bisection); FP64 for every
+// storage form.  A change dg of gamma moves f'_i by beta dg dh_i, so the
+// iteration stops once the last correction moves no population by more than
+// 1e-16 f^eq_i: further digits of gamma cannot change the result, and where
+// dh << ds they are not determined by G to begin with.  Two steps in a row
+// bound the next one (at least quadratic convergence: s_{n+1} <~ s_n^3 /
+// s_{n-1}^2), and when that bound is already below the tolerance the
+// iteration stops without evaluating G again.  From gamma* (first-order
+// accurate) this takes two evaluations on resolved flows.  Returns false,
+// leaving gamma to the caller, when no bracket exists.
+__host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const double (&hw)[27],
+                                                 const double (&cc)[27], double beta, double g0,
+                                                 double& gamma)
 {
-    const double a = 2.0 * beta - 1.0;
     const double inf = __builtin_inf();
     double lo = -inf, hi = inf, hmax = 0.0;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const double ds = (double)ds_of(i), dh = (double)fneq_of(i) - ds;
-        const double w = (double)ifeq_of(i);
-        hmax = fmax(hmax, fabs(dh * w));
-        if (dh != 0.0) {
-            // arg_i > 0  <=>  beta gamma dh_i w < 1 + (dh_i - a ds_i) w
-            const double b = (1.0 + (dh - a * ds) * w) / (beta * dh * w);
-            if (dh > 0.0) hi = fmin(hi, b);
-            else lo = fmax(lo, b);
-        }
+        // 1 + x_i > 0  <=>  beta gamma hw_i < 1 + cc_i (hw_i has the sign of
+        // dh_i; where it is 0 the population gives no bound); no branches, so
+        // that the 27 terms stay one block of code
+        hmax = fmax(hmax, fabs(hw[i]));
+        const double b = (1.0 + cc[i]) / (beta * hw[i]);
+        hi = hw[i] > 0.0 ? fmin(hi, b) : hi;
+        lo = hw[i] < 0.0 ? fmax(lo, b) : lo;
     }
     if (!(lo < hi) || !(lo > -inf) || !(hi < inf)) return false;
     double g = (g0 > lo && g0 < hi) ? g0 : 0.5 * (lo + hi);
     const double dg_tol = 1e-16 / (beta * hmax);
-    double prev = 0.0;   // size of the last Newton step (0: none yet)
+    double prev = 0.0;   // size of the last step (0: none yet)
     for (int it = 0; it < 80; ++it) {
-        double G = 0.0, D = 0.0;
+        // G by the series wherever it holds (no branch per population: one
+        // block of straight code); a node with some |x_i| >= 1/16 sums G
+        // again with the library logarithm
+        double G = 0.0, D1 = 0.0, D2 = 0.0;
+        bool series = true;
+        const double bg = beta * g;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            const double ds = (double)ds_of(i), dh = (double)fneq_of(i) - ds;
-            const double w = (double)ifeq_of(i);
-            const double x = ((1.0 - beta * g) * dh - a * ds) * w;
-            G += dh * log1p_(x);
-            D += dh * dh * w * rcp_refined_(1.0 + x);
+            const double x = cc[i] - bg * hw[i];
+            series = series && log1p_series_ok(x);
+            G += dh[i] * log1p_series(x);
+            const double hr = hw[i] * rcp_refined_(1.0 + x);
+            const double t = dh[i] * hr;
+            D1 += t;
+            D2 += t * hr;
         }
-        const double step = G / (beta * D);      // Newton step, G' = -beta D
+        if (!series) {
+            G = 0.0;
+#pragma unroll
+            for (int i = 0; i < 27; ++i) G += dh[i] * log1p_(cc[i] - bg * hw[i]);
+        }
+        const double GD2 = G * D2, D1s = D1 * D1;
+        const double step = fabs(GD2) <= D1s ? 2.0 * G * D1 / (beta * (2.0 * D1s + GD2))
+                                             : G / (beta * D1);
         const double as = fabs(step);
         if (as <= dg_tol ||                      // converged (also when the step
             (prev > 0.0 && as < prev &&          // is below one ulp of g), or
@@ -407,65 +430,102 @@ __host__ __device__ inline bool gamma_exact_root(DsFn ds_of, FneqFn fneq_of, Ife
     return true;
 }
 
-// Steps 5-7 given ds_i (ds_of(i)), f - f^eq (fneq_of(i)) and the separable
-// 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].  GX selects the exact
-// stabilizer (root of Eq. result1) in place of the estimate gamma*.
-template <typename R, bool GX, typename DsFn, typename FneqFn>
+// dh, gamma and the relaxation, given ds_i (ds_of(i)), f - f^eq (fneq_of(i))
+// and the separable 1/f^eq = iCx[vx+1] * iA9[(vy+1) + 3(vz+1)].  GX selects
+// the exact stabilizer (root of Eq. result1) in place of the estimate gamma*;
+// it then also needs the equilibrium in the stored form (eq_of(i): f^eq_i,
+// or f^eq_i - W_i for the deviation forms, DEV) and in FP64 product form.
+template <typename R, bool GX, bool DEV = false, typename DsFn, typename FneqFn,
+          typename EqFn = int>
 __host__ __device__ __forceinline__ void kbc_gamma_relax(R (&f)[27], DsFn ds_of, FneqFn fneq_of,
                                                          const R (&iCx)[3], const R (&iA9)[9],
-                                                         double rho, const Coll& c, double* gout)
+                                                         double rho, const Coll& c, double* gout,
+                                                         EqFn eq_of = 0)
 {
-    // --- 5-6. dh and the entropic scalar products --------------------------
-    R sh = R(0), hh = R(0);
+    if constexpr (GX) {
+        // The exact root iterates on three FP64 values per population, formed
+        // once here; f itself is not needed again: with x_i = cc_i -
+        // beta gamma hw_i the post-collision population is
+        // f'_i = f^eq_i (1 + x_i) = f_i - beta (2 ds_i + gamma dh_i), so it is
+        // rebuilt from the equilibrium, which keeps the live state small.
+        double dh[27], hw[27], cc[27];
+        R sh = R(0), hh = R(0);
+        const double a = 2.0 * c.beta - 1.0;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R ds = ds_of(i);
-        const R dh = fneq_of(i) - ds;
-        const R w = dh * (iCx[i % 3] * iA9[i / 3]);
-        sh += ds * w;
-        hh += dh * w;
-    }
-    R gamma;
-    if (c.gamma_fixed) {
-        gamma = R(c.gamma_value);
-    } else {
-        // ratio and fallback test in FP64 for every storage form
-        const double hhd = (double)hh, shd = (double)sh;
-        if (hhd <= c.gamma_eps * rho) {
-            gamma = R(2);
-        } else {
-            double g = c.inv_beta - c.c2 * shd / hhd;
-            if constexpr (GX) {
-                double ge;
-                g = gamma_exact_root(ds_of, fneq_of,
-                                     [&](int i) -> R { return iCx[i % 3] * iA9[i / 3]; },
-                                     c.beta, g, ge)
-                        ? ge
-                        : 2.0;
-            }
-            gamma = R(g);
+        for (int i = 0; i < 27; ++i) {
+            const R ds = ds_of(i);
+            const R fneq = fneq_of(i);
+            const R w = iCx[i % 3] * iA9[i / 3];
+            const R wr = (fneq - ds) * w;
+            sh += ds * wr;
+            hh += (fneq - ds) * wr;
+            const double dsd = (double)ds, wd = (double)w;
+            dh[i] = (double)fneq - dsd;
+            hw[i] = dh[i] * wd;
+            cc[i] = (dh[i] - a * dsd) * wd;
         }
-    }
-
-    if (gout) *gout = (double)gamma;
-
-    // --- 7. relax: f' = f - beta (2 ds + gamma dh), evaluated with
-    // dh = (f - f^eq) - ds as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
-    const R c1 = R(c.beta) * (R(2) - gamma);
-    const R c2 = R(c.beta) * gamma;
+        double gamma;
+        if (c.gamma_fixed) {
+            gamma = c.gamma_value;
+        } else if ((double)hh <= c.gamma_eps * rho) {
+            gamma = 2.0;
+        } else {
+            const double g0 = c.inv_beta - c.c2 * (double)sh / (double)hh;
+            double ge;
+            gamma = gamma_exact_root(dh, hw, cc, c.beta, g0, ge) ? ge : 2.0;
+        }
+        if (gout) *gout = gamma;
+        const double bg = c.beta * gamma;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const R ds = ds_of(i);
-        const R fneq = fneq_of(i);
-        f[i] = f[i] - c1 * ds - c2 * fneq;
+        for (int i = 0; i < 27; ++i) {
+            const double eq = eq_of(i);
+            const double feq = DEV ? eq + weight(i) : eq;
+            f[i] = R(eq + feq * (cc[i] - bg * hw[i]));
+        }
+        return;
+    } else {
+        // dh and the entropic scalar products of Eq. result21
+        R sh = R(0), hh = R(0);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const R ds = ds_of(i);
+            const R dh = fneq_of(i) - ds;
+            const R w = dh * (iCx[i % 3] * iA9[i / 3]);
+            sh += ds * w;
+            hh += dh * w;
+        }
+        R gamma;
+        if (c.gamma_fixed) {
+            gamma = R(c.gamma_value);
+        } else {
+            // ratio and fallback test in FP64 for every storage form
+            const double hhd = (double)hh, shd = (double)sh;
+            if (hhd <= c.gamma_eps * rho) gamma = R(2);
+            else gamma = R(c.inv_beta - c.c2 * shd / hhd);
+        }
+
+        if (gout) *gout = (double)gamma;
+
+        // relaxation f' = f - beta (2 ds + gamma dh) (Eq. Egeneral with the
+        // mirror state of Eq. ksh-mirror), evaluated with dh = (f - f^eq) - ds
+        // as f' = f - beta (2 - gamma) ds - beta gamma (f - f^eq)
+        const R c1 = R(c.beta) * (R(2) - gamma);
+        const R c2 = R(c.beta) * gamma;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const R ds = ds_of(i);
+            const R fneq = fneq_of(i);
+            f[i] = f[i] - c1 * ds - c2 * fneq;
+        }
     }
 }
 
-// Steps 3-7 for the natural-moment variants: ds_i from table s_parts.
-template <typename R, int V, bool GX, typename FneqFn>
+// Natural-moment variants: ds_i from table s_parts, then kbc_gamma_relax.
+template <typename R, int V, bool GX, bool DEV, typename FneqFn, typename EqFn>
 __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d, FneqFn fneq_of,
                                                    const R (&iCx)[3], const R (&iA9)[9],
-                                                   double rho, const Coll& c, double* gout)
+                                                   double rho, const Coll& c, double* gout,
+                                                   EqFn eq_of)
 {
     constexpr bool WT = with_t(V);
     constexpr bool WQ = with_q(V);
@@ -500,10 +560,10 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
         }
         return R(sx * sy * sz) * qC;
     };
-    kbc_gamma_relax<R, GX>(f, ds_of, fneq_of, iCx, iA9, rho, c, gout);
+    kbc_gamma_relax<R, GX, DEV>(f, ds_of, fneq_of, iCx, iA9, rho, c, gout, eq_of);
 }
 
-// Steps 3-7 for the central-moment variants (section IV; appendix).  The
+// Central-moment variants (section IV; appendix), then kbc_gamma_relax.  The
 // shear part is rebuilt from central moments of f - f^eq about the node's u.
 // Because f - f^eq carries no mass and no momentum, its second-order central
 // moments equal the natural ones, and a third-order one is the natural one
@@ -516,11 +576,12 @@ __host__ __device__ __forceinline__ void kbc_relax(R (&f)[27], const DMom<R>& d,
 //   f_{+1} = (u^2 + u)/2 m0 + (u + 1/2) m1 + m2/2,
 // so ds~ is three separable passes over a 3x3x3 array that holds only the
 // 13 second- and third-order entries kept in s.
-template <typename R, int V, bool GX, typename FneqFn>
+template <typename R, int V, bool GX, bool DEV, typename FneqFn, typename EqFn>
 __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMom<R>& d,
                                                            const R (&u)[3], FneqFn fneq_of,
                                                            const R (&iCx)[3], const R (&iA9)[9],
-                                                           double rho, const Coll& c, double* gout)
+                                                           double rho, const Coll& c, double* gout,
+                                                           EqFn eq_of)
 {
     constexpr bool WT = with_t(V);
     constexpr bool WQ = with_q(V);
@@ -594,7 +655,8 @@ __host__ __device__ __forceinline__ void kbc_relax_central(R (&f)[27], const DMo
                 ds[vx + 3 * vy + 9 * vz] = G[0][vx][0] * Z2[0][vy][vz] +
                                            G[0][vx][1] * Z2[1][vy][vz] +
                                            G[0][vx][2] * Z2[2][vy][vz];
-    kbc_gamma_relax<R, GX>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c, gout);
+    kbc_gamma_relax<R, GX, DEV>(f, [&](int i) -> R { return ds[i]; }, fneq_of, iCx, iA9, rho, c,
+                                gout, eq_of);
 }
 
 // gout, when given, receives the gamma used at this node.
@@ -606,7 +668,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
     constexpr bool DEV = Traits<S>::kDev;
 
     if constexpr (Traits<S>::kMixed) {
-        // --- 1-2 in FP64: rho, u and f - f^eq from the deviations g --------
+        // rho, u and f - f^eq from the deviations g, in FP64
         double X0[9], X1[9];
 #pragma unroll
         for (int yz = 0; yz < 9; ++yz) {
@@ -644,7 +706,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
                 fneq[3 * yz + ax] = (R)((double)f[3 * yz + ax] - geq);
             }
         }
-        // --- 3-4 in FP32: the moment differences are moments of f - f^eq ----
+        // in FP32: the moment differences are moments of f - f^eq
         R M[3][3][3];
         moments27<R>(fneq, M);
         DMom<R> d;
@@ -677,14 +739,22 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) iCx[ax] = (R)irho * iE[0][ax];
         auto fneq_of = [&](int i) -> R { return fneq[i]; };
+        // f^eq - W in FP64, re-formed where the exact stabilizer needs it
+        auto eq_of = [&](int i) -> double {
+            const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
+            const double A = E[1][ay] * E[2][az];
+            const double B = dE[1][ay] * E[2][az] + w1(ay - 1) * dE[2][az];
+            const double C = dE[0][ax] + drho * E[0][ax];
+            return A * C + w1(ax - 1) * B;
+        };
         if constexpr (is_central(V)) {
             const R uf[3] = {(R)u[0], (R)u[1], (R)u[2]};
-            kbc_relax_central<R, V, GX>(f, d, uf, fneq_of, iCx, iA9, rho, c, gout);
+            kbc_relax_central<R, V, GX, true>(f, d, uf, fneq_of, iCx, iA9, rho, c, gout, eq_of);
         } else {
-            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, rho, c, gout);
+            kbc_relax<R, V, GX, true>(f, d, fneq_of, iCx, iA9, rho, c, gout, eq_of);
         }
     } else {
-        // --- 1. raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2) ----
+        // raw moments R_pqr = sum_i f_i vx^p vy^q vz^r (p,q,r <= 2)
         R M[3][3][3];
         moments27<R>(f, M);
         // rho and u (deviation forms: rho = 1 + sum g, sum v W = 0)
@@ -693,7 +763,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
         const R irho = rcp_(rho);
         const R u[3] = {M[1][0][0] * irho, M[0][1][0] * irho, M[0][0][1] * irho};
 
-        // --- 2. one-dimensional equilibrium marginals ----------------------
+        // one-dimensional equilibrium marginals (Eq. entropic_eq)
         R E[3][3], dE[3][3], dm2[3], m2[3], iE[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -702,7 +772,7 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             recip3<R>(E[a], iE[a]);
         }
 
-        // --- 3-4. moment differences; equilibrium moments in closed form ---
+        // moment differences; equilibrium moments in closed form:
         // rho m_p(u_x) m_q(u_y) m_r(u_z); the second-order diagonal ones
         // carry the weights' share 1/3 in the deviation forms
         R dD[3];
@@ -753,10 +823,17 @@ __host__ __device__ __forceinline__ void collide(typename Traits<S>::R (&f)[27],
             if constexpr (DEV) return f[i] - (A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
             else return f[i] - A9[yz] * Cx[ax];
         };
+        // the equilibrium in the stored form (f^eq, or f^eq - W)
+        auto eq_of = [&](int i) -> double {
+            const int ax = i % 3, yz = i / 3;
+            if constexpr (DEV) return (double)(A9[yz] * Cx[ax] + R(w1(ax - 1)) * B9[yz]);
+            else return (double)(A9[yz] * Cx[ax]);
+        };
         if constexpr (is_central(V))
-            kbc_relax_central<R, V, GX>(f, d, u, fneq_of, iCx, iA9, (double)rho, c, gout);
+            kbc_relax_central<R, V, GX, DEV>(f, d, u, fneq_of, iCx, iA9, (double)rho, c, gout,
+                                             eq_of);
         else
-            kbc_relax<R, V, GX>(f, d, fneq_of, iCx, iA9, (double)rho, c, gout);
+            kbc_relax<R, V, GX, DEV>(f, d, fneq_of, iCx, iA9, (double)rho, c, gout, eq_of);
     }
 }
 

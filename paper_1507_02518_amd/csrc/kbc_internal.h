@@ -65,6 +65,11 @@ void set_last_error(const char* msg);
 hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
                        hipStream_t stream);
 
+// The kernel and launch shape launch_step uses (for building graphs of steps).
+using StepFn = void (*)(StepParams);
+hipError_t step_launch_shape(int storage, int variant, int sweep, bool exact_gamma, const Geom& g,
+                             StepFn* fn, uint32_t* grid, uint32_t* block);
+
 // Write f^eq(rho, u) of device fields u [3][N], rho [N] (may be NULL) into the
 // storage buffer in the given layout.
 hipError_t launch_init_feq(int storage, int layout, void* buf, const Geom& g,
@@ -179,7 +184,6 @@ hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* 
 struct LoadCtx {
     float inv_scale[27];
 };
-using StepFn = void (*)(StepParams);
 using PoolFn = void (*)(const PoolBox*, const uint32_t*, const PoolMeta*, int);
 using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
 

@@ -167,18 +167,19 @@ __global__ void __launch_bounds__(kBlock) k_scatter_pop(int layout, void* buf, G
     }
 }
 
-// rho = sum_i f_i, rho u = sum_i v_i f_i (section I), in FP64.  Deviation
-// forms sum the stored deviations and add the weights' share (1, 0).
+// rho = sum_i f_i, rho u = sum_i v_i f_i (section I) of node n, in FP64.
+// Deviation forms sum the stored deviations and add the weights' share
+// (1, 0).  Every kernel that needs the velocity of F(t) takes it from here,
+// so they all see the same bits.
 template <int S>
-__global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf, Geom g, LoadCtx lc,
-                                                    double* __restrict__ rho,
-                                                    double* __restrict__ u, int* flag)
+__device__ __forceinline__ void node_velocity(int layout, const void* buf, const Geom& g,
+                                              const LoadCtx& lc, uint32_t n, double& m,
+                                              double& ux, double& uy, double& uz)
 {
-    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.nnodes) return;
     uint32_t x, y, z;
     node_xyz(n, g, x, y, z);
-    double m = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+    m = 0.0;
     for (int i = 0; i < 27; ++i) {
         int slot;
         const uint64_t idx = locate(layout, i, x, y, z, g, slot);
@@ -191,7 +192,20 @@ __global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf,
     }
     if constexpr (S != ST_F64) m += 1.0;
     const double ir = 1.0 / m;
-    const double ux = jx * ir, uy = jy * ir, uz = jz * ir;
+    ux = jx * ir;
+    uy = jy * ir;
+    uz = jz * ir;
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock) k_moments(int layout, const void* buf, Geom g, LoadCtx lc,
+                                                    double* __restrict__ rho,
+                                                    double* __restrict__ u, int* flag)
+{
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnodes) return;
+    double m, ux, uy, uz;
+    node_velocity<S>(layout, buf, g, lc, n, m, ux, uy, uz);
     if (rho) rho[n] = m;
     u[n] = ux;
     u[g.nnodes + n] = uy;
@@ -480,17 +494,16 @@ __global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
-                       hipStream_t stream)
+hipError_t step_launch_shape(int storage, int variant, int sweep, bool exact_gamma, const Geom& g,
+                             StepFn* fn, uint32_t* grid, uint32_t* block)
 {
     // the AA kernels address populations in planes (see node_update)
-    if (sweep != SW_PULL && !geom_is_planes(p.g)) return hipErrorInvalidValue;
-    StepFn fn;
+    if (sweep != SW_PULL && !geom_is_planes(g)) return hipErrorInvalidValue;
     switch (storage) {
-    case ST_F64: fn = exact_gamma ? step_kernel<ST_F64, true>(variant, sweep) : step_kernel<ST_F64, false>(variant, sweep); break;
-    case ST_F32: fn = exact_gamma ? step_kernel<ST_F32, true>(variant, sweep) : step_kernel<ST_F32, false>(variant, sweep); break;
-    case ST_F32X: fn = exact_gamma ? step_kernel<ST_F32X, true>(variant, sweep) : step_kernel<ST_F32X, false>(variant, sweep); break;
-    default: fn = exact_gamma ? step_kernel<ST_F16, true>(variant, sweep) : step_kernel<ST_F16, false>(variant, sweep); break;
+    case ST_F64: *fn = exact_gamma ? step_kernel<ST_F64, true>(variant, sweep) : step_kernel<ST_F64, false>(variant, sweep); break;
+    case ST_F32: *fn = exact_gamma ? step_kernel<ST_F32, true>(variant, sweep) : step_kernel<ST_F32, false>(variant, sweep); break;
+    case ST_F32X: *fn = exact_gamma ? step_kernel<ST_F32X, true>(variant, sweep) : step_kernel<ST_F32X, false>(variant, sweep); break;
+    default: *fn = exact_gamma ? step_kernel<ST_F16, true>(variant, sweep) : step_kernel<ST_F16, false>(variant, sweep); break;
     }
     // One wavefront per workgroup for the exact stabilizer (one wave per
     // SIMD: 64-thread workgroups fill the CUs more evenly; at 256^3 the pull
@@ -498,8 +511,19 @@ hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, co
     // AA sweeps 12% and 8%), kStepBlock threads otherwise (64 measured within
     // +-2% for the other pull forms, 5% slower for FP16 pull, and 17-33%
     // slower for the AA sweeps).
-    const uint32_t block = exact_gamma ? 64u : (uint32_t)kStepBlock;
-    hipLaunchKernelGGL(fn, dim3((p.g.nnodes + block - 1) / block), dim3(block), 0, stream, p);
+    *block = exact_gamma ? 64u : (uint32_t)kStepBlock;
+    *grid = (g.nnodes + *block - 1) / *block;
+    return hipSuccess;
+}
+
+hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, const StepParams& p,
+                       hipStream_t stream)
+{
+    StepFn fn;
+    uint32_t grid, block;
+    hipError_t e = step_launch_shape(storage, variant, sweep, exact_gamma, p.g, &fn, &grid, &block);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, p);
     return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ constexpr int kBlock = 256;
 #ifndef KBC_NT_LOAD
 #define KBC_NT_LOAD 0
 #endif
+#ifndef KBC_AA_ALIGNED
+#define KBC_AA_ALIGNED 1
+#endif
 constexpr int kStepBlock = KBC_STEP_BLOCK;
 
 template <typename T>
@@ -62,9 +65,19 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
 // in-place update is free of races between nodes.
 typedef __attribute__((address_space(1))) char gchar_t;
 
-template <int S, int V, int SW, bool GX = false>
+// ALN (AA odd sweep of a single box): line-aligned stores.  The value that
+// node x sends to x + v_i is stored by the thread of node x + v_x of the
+// same row (its own x, so each store instruction of a wave covers whole cache
+// lines); the values cross between threads through LDS after the collision.
+// Where that thread is not in the workgroup (a row split between
+// workgroups) the owner stores its value itself, as without ALN.  n0: first
+// node of the workgroup's contiguous range of blockDim.x nodes; `store`:
+// whether this thread's node is real (a thread past the last node takes the
+// last node's inputs, so its LDS entries are defined, and stores nothing).
+template <int S, int V, int SW, bool GX = false, bool ALN = false>
 __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
-                                            const Coll& c, const int8_t* sexp, uint32_t n)
+                                            const Coll& c, const int8_t* sexp, uint32_t n,
+                                            uint32_t n0 = 0, bool store = true)
 {
     using T = typename Traits<S>::T;
     using R = typename Traits<S>::R;
@@ -169,31 +182,77 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
         fz[2] = (z2 + 1 == g.nz ? 0 : z2 + 1) * slabb;
     }
 
+    if constexpr (ALN) {
+        static_assert(SW == SW_AA_ODD, "aligned stores are for the odd AA sweep");
+        // the 18 directions with v_x != 0 cross lanes: slot k = 2 (i / 3) +
+        // (v_x > 0)
+        __shared__ T xch[18][kStepBlock];
+        const uint32_t t = threadIdx.x, nb_ = blockDim.x;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
-        if constexpr (SW == SW_PULL) {
-            st(i, nb, encode_exp<S>(f[i], ex(i)));
-        } else if constexpr (SW == SW_AA_EVEN) {
-            st(opp(i), nb, encode_exp<S>(f[i], ex(i)));
-        } else {
-            st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
+        for (int i = 0; i < 27; ++i)
+            if (i % 3 != 1) xch[2 * (i / 3) + (i % 3 == 2)][t] = encode_exp<S>(f[i], ex(i));
+        __syncthreads();
+        // node index of (0, y, z) relative to the workgroup's first node;
+        // unsigned arithmetic: a node outside [n0, n0 + blockDim) maps to an
+        // index >= blockDim
+        const uint32_t row0 = n - x - n0;
+        const uint32_t xl = x == 0 ? g.nx - 1 : x - 1, xr = x + 1 == g.nx ? 0 : x + 1;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
+            if (ax == 1) {
+                if (store) st(i, fz[az] + fy[ay] + fx[1], encode_exp<S>(f[i], ex(i)));
+            } else {
+                // the value that lands on this x comes from x - v_x; this
+                // node's own value goes to x + v_x
+                const uint32_t src = row0 + (ax == 2 ? xl : xr);
+                const uint32_t dst = row0 + (ax == 2 ? xr : xl);
+                if (store && src < nb_)
+                    st(i, fz[az] + fy[ay] + fx[1], xch[2 * (i / 3) + (ax == 2)][src]);
+                if (store && dst >= nb_)
+                    st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
+            if constexpr (SW == SW_PULL) {
+                st(i, nb, encode_exp<S>(f[i], ex(i)));
+            } else if constexpr (SW == SW_AA_EVEN) {
+                st(opp(i), nb, encode_exp<S>(f[i], ex(i)));
+            } else {
+                st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
+            }
         }
     }
 }
 
 // Fused step of one box: one thread per node, workgroups of up to
 // kStepBlock threads (the launch picks the size).  GX: exact stabilizer.
+#ifndef KBC_GX_WAVES_PER_EU
+#define KBC_GX_WAVES_PER_EU 1
+#endif
 template <int S, int V, int SW, bool GX>
 __global__ void __launch_bounds__(kStepBlock)
 #if KBC_WAVES_PER_EU
 __attribute__((amdgpu_waves_per_eu(KBC_WAVES_PER_EU, 8)))
+#else
+__attribute__((amdgpu_waves_per_eu(GX ? KBC_GX_WAVES_PER_EU : 1, 8)))
 #endif
 k_step(StepParams p)
 {
-    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.g.nnodes) return;
-    node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
+    const uint32_t n0 = blockIdx.x * blockDim.x;
+    const uint32_t n = n0 + threadIdx.x;
+    if constexpr (SW == SW_AA_ODD && !GX && KBC_AA_ALIGNED) {
+        // every thread reaches the workgroup barrier of the aligned stores
+        const bool real = n < p.g.nnodes;
+        node_update<S, V, SW, GX, true>(p.src, p.dst, p.g, p.c, p.scale_exp,
+                                        real ? n : p.g.nnodes - 1, n0, real);
+    } else {
+        if (n >= p.g.nnodes) return;
+        node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
+    }
 }
 
 typedef __attribute__((address_space(1))) char gchar;
@@ -319,8 +378,8 @@ __device__ __forceinline__ void block_sum(double (&acc)[K], double* out)
 }
 
 // Per-block sums of gamma and gamma^2 and the block's min and max of the
-// stabilizer that the next step would use at each node (the collision up to
-// step 6 on the stored state; nothing is written back).
+// stabilizer that the next step would use at each node (the collision on the
+// stored state as far as gamma; nothing is written back).
 template <int S, int V, bool GX>
 __global__ void __launch_bounds__(kBlock) k_gamma_stats(int layout, const void* buf, Geom g, Coll c,
                                                         LoadCtx lc, double* __restrict__ partial)
