@@ -35,6 +35,9 @@ constexpr int kBlock = 256;
 #ifndef KBC_AA_ALIGNED
 #define KBC_AA_ALIGNED 1
 #endif
+#ifndef KBC_XCD_REMAP
+#define KBC_XCD_REMAP 0
+#endif
 constexpr int kStepBlock = KBC_STEP_BLOCK;
 
 template <typename T>
@@ -65,7 +68,8 @@ __device__ __forceinline__ uint32_t node_of(uint32_t x, uint32_t y, uint32_t z, 
 // in-place update is free of races between nodes.
 typedef __attribute__((address_space(1))) char gchar_t;
 
-// ALN (AA odd sweep of a single box): line-aligned stores.  The value that
+// ALN (AA odd sweep of a single box, FP64 and FP32-X storage): line-aligned
+// stores.  The value that
 // node x sends to x + v_i is stored by the thread of node x + v_x of the
 // same row (its own x, so each store instruction of a wave covers whole cache
 // lines); the values cross between threads through LDS after the collision.
@@ -188,9 +192,19 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
         // (v_x > 0)
         __shared__ T xch[18][kStepBlock];
         const uint32_t t = threadIdx.x, nb_ = blockDim.x;
+        // directions with v_x = 0 stay in their lane and are stored at once
+        // (a location is read only by the node that writes it, which has
+        // loaded its inputs already); the others go through LDS, so no
+        // population stays in a register across the barrier
 #pragma unroll
-        for (int i = 0; i < 27; ++i)
-            if (i % 3 != 1) xch[2 * (i / 3) + (i % 3 == 2)][t] = encode_exp<S>(f[i], ex(i));
+        for (int i = 0; i < 27; ++i) {
+            const int ay = (i / 3) % 3, az = i / 9;
+            if (i % 3 == 1) {
+                if (store) st(i, fz[az] + fy[ay] + fx[1], encode_exp<S>(f[i], ex(i)));
+            } else {
+                xch[2 * (i / 3) + (i % 3 == 2)][t] = encode_exp<S>(f[i], ex(i));
+            }
+        }
         __syncthreads();
         // node index of (0, y, z) relative to the workgroup's first node;
         // unsigned arithmetic: a node outside [n0, n0 + blockDim) maps to an
@@ -200,32 +214,51 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
-            if (ax == 1) {
-                if (store) st(i, fz[az] + fy[ay] + fx[1], encode_exp<S>(f[i], ex(i)));
-            } else {
-                // the value that lands on this x comes from x - v_x; this
-                // node's own value goes to x + v_x
-                const uint32_t src = row0 + (ax == 2 ? xl : xr);
-                const uint32_t dst = row0 + (ax == 2 ? xr : xl);
-                if (store && src < nb_)
-                    st(i, fz[az] + fy[ay] + fx[1], xch[2 * (i / 3) + (ax == 2)][src]);
-                if (store && dst >= nb_)
-                    st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
-            }
+            if (ax == 1) continue;
+            const int k = 2 * (i / 3) + (ax == 2);
+            // the value that lands on this x comes from x - v_x; this node's
+            // own value goes to x + v_x
+            const uint32_t src = row0 + (ax == 2 ? xl : xr);
+            const uint32_t dst = row0 + (ax == 2 ? xr : xl);
+            if (store && src < nb_) st(i, fz[az] + fy[ay] + fx[1], xch[k][src]);
+            if (store && dst >= nb_) st(i, fz[az] + fy[ay] + fx[ax], xch[k][t]);
         }
     } else {
+        // the stores at the node's own offset: a copy the compiler cannot
+        // tie to the loads' 64-bit address arithmetic keeps every store in
+        // the scalar-base + 32-bit-offset form (without it each store takes a
+        // 64-bit vector add, 27 VALU instructions per node)
+        uint32_t nbs = nb;
+        if constexpr (SW != SW_AA_ODD) asm volatile("" : "+v"(nbs));
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const int ax = i % 3, ay = (i / 3) % 3, az = i / 9;
             if constexpr (SW == SW_PULL) {
-                st(i, nb, encode_exp<S>(f[i], ex(i)));
+                st(i, nbs, encode_exp<S>(f[i], ex(i)));
             } else if constexpr (SW == SW_AA_EVEN) {
-                st(opp(i), nb, encode_exp<S>(f[i], ex(i)));
+                st(opp(i), nbs, encode_exp<S>(f[i], ex(i)));
             } else {
                 st(i, fz[az] + fy[ay] + fx[ax], encode_exp<S>(f[i], ex(i)));
             }
         }
     }
+}
+
+// Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals
+// workgroups to the eight XCDs in turn).  With KBC_XCD_REMAP (a build
+// option, off by default) each XCD takes one contiguous eighth of the box
+// instead: XCD j's k-th workgroup gets range start(j) + k, so that
+// workgroups sharing cache lines (the two ends of a row split between
+// workgroups, read shifted by one node in x) meet in one L2.  Measured on
+// MI355X: FP64 AA at 512^3 7% faster, but FP64 AA at 256^3 10% and the pull
+// sweep 1.4% slower, FP32/FP16 AA at 512^3 1-2% slower (eight separate
+// fronts through HBM instead of one).  The exact stabilizer (ALU-bound,
+// one-wave workgroups) keeps the plain order in any case.
+__device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, bool exact)
+{
+    if (!KBC_XCD_REMAP || exact) return b;
+    const uint32_t j = b & 7u, k = b >> 3, q = grid >> 3, r = grid & 7u;
+    return j * q + (j < r ? j : r) + k;
 }
 
 // Fused step of one box: one thread per node, workgroups of up to
@@ -242,9 +275,13 @@ __attribute__((amdgpu_waves_per_eu(GX ? KBC_GX_WAVES_PER_EU : 1, 8)))
 #endif
 k_step(StepParams p)
 {
-    const uint32_t n0 = blockIdx.x * blockDim.x;
+    const uint32_t n0 = step_block(blockIdx.x, gridDim.x, GX) * blockDim.x;
     const uint32_t n = n0 + threadIdx.x;
-    if constexpr (SW == SW_AA_ODD && !GX && KBC_AA_ALIGNED) {
+    // aligned stores where the exchange costs no occupancy: FP64 (2 waves
+    // per SIMD either way) and FP32 with the FP64-formed non-equilibrium (3);
+    // the plain FP32 and FP16 sweeps would drop from 4 waves to 3 (FP32 at
+    // 512^3 measured 5% slower with the exchange)
+    if constexpr (SW == SW_AA_ODD && !GX && KBC_AA_ALIGNED && (S == ST_F64 || S == ST_F32X)) {
         // every thread reaches the workgroup barrier of the aligned stores
         const bool real = n < p.g.nnodes;
         node_update<S, V, SW, GX, true>(p.src, p.dst, p.g, p.c, p.scale_exp,

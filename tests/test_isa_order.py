@@ -56,8 +56,9 @@ def _kernels(asm, pattern):
 
 
 def test_aa_step_kernels_load_everything_before_storing(asm):
-    """27 population loads, then only stores: 27 in the even sweep and in the
-    exact-stabilizer odd sweep; 45 in the odd sweep with aligned stores (9
+    """27 population loads, then only stores: 27 in the even sweep, in the
+    exact-stabilizer odd sweep and in the plain FP32 and FP16 odd sweeps; 45
+    in the FP64 and FP32-X odd sweeps, whose stores are line-aligned (9
     directions with v_x = 0, 18 aligned, 18 for rows split between
     workgroups, of which a thread executes at most 27)."""
     ks = _kernels(asm, r"k_stepILi\dELi\dELi[12]E")
@@ -66,7 +67,7 @@ def test_aa_step_kernels_load_everything_before_storing(asm):
     for nm, ops in ks.items():
         loads = [op for op in ops if "load" in op]
         stores = [op for op in ops if "store" in op]
-        odd_aligned = re.search(r"k_stepILi\dELi\dELi2ELb0E", nm) is not None
+        odd_aligned = re.search(r"k_stepILi[03]ELi\dELi2ELb0E", nm) is not None
         assert len(loads) == 27, (nm, len(loads))
         assert len(stores) == (45 if odd_aligned else 27), (nm, len(stores))
         first_store = next(i for i, op in enumerate(ops) if "store" in op)
