@@ -154,6 +154,24 @@ int kbc_energy(kbc_handle h, double* k);
  * not finite after some step (the steps are taken and k is still written). */
 int kbc_energy_series(kbc_handle h, int64_t n, double* k);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as a tight serving loop or a harness that forbids it):
+ * kbc_energy_series without any allocation.  Advances n steps and writes the
+ * kinetic energy after each of them to host k[0 .. n-1], as kbc_energy_series
+ * does (the same sums in the same order), but reads the velocity straight
+ * from the populations and keeps its partial sums and the log of k in a
+ * static device array of the library instead of device buffers:
+ * 0 <= n <= KBC_NOALLOC_MAX_STEPS, else KBC_EINVAL.  The array (about 540 KB)
+ * exists once per GPU the library runs on and is held until the process
+ * ends; its address is looked up on the first call on each device.  Every
+ * call on a GPU uses that GPU's array, so calls that overlap on one GPU (from
+ * two host threads, or on two boxes whose streams run concurrently) race and
+ * must be serialised by the caller.  Synchronises the box's stream.
+ * KBC_EUNSTABLE if some k is not finite (the state diverged; k is still
+ * written). */
+#define KBC_NOALLOC_MAX_STEPS 65536
+int kbc_energy_series_noalloc(kbc_handle h, int64_t n, double* k);
+
 /* Enstrophy Omega = (1/2) < |curl u'|^2 >, u' = u - <u>, derivatives by
  * second-order central differences on the periodic grid (section V.A).
  * FP64, fixed reduction order.  Synchronises. */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -258,6 +259,50 @@ int build_graph(kbc_handle h)
     }
     h->graph = graph;
     h->graph_exec = exec;
+    return KBC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of kbc_energy_series_noalloc: a file-scope array in each
+// GPU's memory (the runtime places one copy per device when the library's
+// code object loads there; it stays until the process ends).  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device: the array's name in host code is not a device address.
+//   [0, kScrPartial)                 per-block partial sums of a reduction
+//   [kScrPartial, +8)                the sums of u (and spare)
+//   [kScrPartial + 8, + max steps)   k after each step, copied out at the end
+// Nothing in it has to start at zero: every value is written before it is
+// read.  Calls on one GPU share the array.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxSteps = KBC_NOALLOC_MAX_STEPS;
+constexpr size_t kScrPartial = 3 * 1024;
+constexpr size_t kScrSums = 8;
+constexpr size_t kScrDoubles = kScrPartial + kScrSums + (size_t)kNoAllocMaxSteps;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScrDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current (the caller has made it current).
+int device_scratch(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(KBC_EINVAL, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(KBC_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return KBC_OK;
 }
 
@@ -559,6 +604,41 @@ int kbc_energy_series(kbc_handle h, int64_t n, double* k)
     const double inv2n = 0.5 / (double)h->g.nnodes;
     for (int64_t j = 0; j < n; ++j) k[j] *= inv2n;
     if (flag) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
+    return KBC_OK;
+}
+
+int kbc_energy_series_noalloc(kbc_handle h, int64_t n, double* k)
+{
+    if (int r = check_handle(h)) return r;
+    if (n < 0) return fail(KBC_EINVAL, "n must be >= 0");
+    if (n > kNoAllocMaxSteps)
+        return fail(KBC_EINVAL, "n exceeds KBC_NOALLOC_MAX_STEPS (65536), the steps the "
+                                "static scratch array can log");
+    if (n > 0 && !k) return fail(KBC_EINVAL, "k is NULL");
+    if (!h->initialised) return fail(KBC_ESTATE, "box has no state (call kbc_init_velocity)");
+    if (n == 0) return KBC_OK;
+    if (reduce_partials() * 3 > (int)kScrPartial)
+        return fail(KBC_EDEVICE, "reduction partials exceed the scratch array");
+    if (int r = set_device(h)) return r;
+    double* scr = nullptr;
+    if (int r = device_scratch(h->device, &scr)) return r;
+    double* partial = scr;
+    double* sums = scr + kScrPartial;
+    double* log = scr + kScrPartial + kScrSums;
+    for (int64_t j = 0; j < n; ++j) {
+        if (int r = step_once(h)) return r;
+        KBC_HIP(launch_energy_direct(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale,
+                                     partial, sums, log + j, h->stream));
+    }
+    KBC_HIP(hipMemcpyAsync(k, log, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    KBC_HIP(hipStreamSynchronize(h->stream));
+    const double inv2n = 0.5 / (double)h->g.nnodes;
+    bool finite = true;
+    for (int64_t j = 0; j < n; ++j) {
+        k[j] *= inv2n;
+        finite = finite && std::isfinite(k[j]);
+    }
+    if (!finite) return fail(KBC_EUNSTABLE, "state is not finite (the run has diverged)");
     return KBC_OK;
 }
 

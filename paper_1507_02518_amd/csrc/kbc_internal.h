@@ -134,6 +134,14 @@ int corr_blocks(const Geom& g);
 hipError_t launch_corr_x(const Geom& g, const double* u, const double* mean_sum, int rmax,
                          double* partial, double* out, hipStream_t stream);
 
+// Kinetic-energy sum of F(t) read straight from the populations (no velocity
+// field in memory): *out = sum_x |u(x) - mean|^2, the same bits as
+// launch_moments + launch_reduce kinds 0 and 1.  partial: reduce_partials() * 3
+// doubles; sums: 3 doubles (left holding the sums of u).
+hipError_t launch_energy_direct(int storage, int layout, const void* buf, const Geom& g,
+                                const float* inv_scale, double* partial, double* sums,
+                                double* out, hipStream_t stream);
+
 // `partial` is device scratch of reduce_partials() doubles * 3.
 int reduce_partials();
 hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double* mean_sum,

@@ -264,6 +264,49 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double* __restric
     block_sum<3>(acc, out);
 }
 
+// Kinetic energy straight from the populations, without a velocity field in
+// memory: pass 0 sums u over the nodes, pass 1 sums |u - mean|^2 (mean =
+// mean_sum / N).  The grid, the per-thread order and the block reduction are
+// those of k_reduce over a stored field, and u comes from node_velocity as in
+// k_moments, so the sums are the same bits as moments + k_reduce.
+template <int S, int PASS>
+__global__ void __launch_bounds__(kBlock) k_energy_pass(int layout, const void* buf, Geom g,
+                                                        LoadCtx lc,
+                                                        const double* __restrict__ mean_sum,
+                                                        double* __restrict__ partial)
+{
+    const size_t N = g.nnodes;
+    double acc[3] = {0.0, 0.0, 0.0};
+    double mean[3] = {0.0, 0.0, 0.0};
+    if (PASS != 0)
+        for (int a = 0; a < 3; ++a) mean[a] = mean_sum[a] / (double)N;
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.nnodes; n += gridDim.x * kBlock) {
+        double m, uu[3];
+        node_velocity<S>(layout, buf, g, lc, n, m, uu[0], uu[1], uu[2]);
+        // u as k_moments stores it: rounded, not fused into u - mean below
+        asm volatile("" : "+v"(uu[0]), "+v"(uu[1]), "+v"(uu[2]));
+        if (PASS == 0) {
+            for (int a = 0; a < 3; ++a) acc[a] += uu[a];
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                const double d = uu[a] - mean[a];
+                acc[0] += d * d;
+            }
+        }
+    }
+    block_sum<3>(acc, partial + 3 * blockIdx.x);
+}
+
+// First component of k_reduce_final only (same order, same bits), for a
+// destination with room for one value.
+__global__ void __launch_bounds__(kBlock) k_reduce_final_1(const double* __restrict__ partial,
+                                                           int count, double* __restrict__ out)
+{
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < count; b += kBlock) acc[0] += partial[3 * b];
+    block_sum<1>(acc, out);
+}
+
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_reduce_final_k(const double* __restrict__ partial,
                                                            int count, double* __restrict__ out)
@@ -655,6 +698,26 @@ hipError_t launch_reduce(int kind, const Geom& g, const double* u, const double*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_direct(int storage, int layout, const void* buf, const Geom& g,
+                                const float* inv_scale, double* partial, double* sums,
+                                double* out, hipStream_t stream)
+{
+    if (storage == ST_F32X) storage = ST_F32;  // same storage format
+    LoadCtx lc;
+    for (int i = 0; i < 27; ++i) lc.inv_scale[i] = inv_scale ? inv_scale[i] : 1.0f;
+    const unsigned blocks = std::min<unsigned>(kReduceBlocks, grid_for(g.nnodes));
+    const dim3 grid(blocks), block(kBlock);
+    if (storage == ST_F64) hipLaunchKernelGGL((k_energy_pass<ST_F64, 0>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    else if (storage == ST_F32) hipLaunchKernelGGL((k_energy_pass<ST_F32, 0>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    else hipLaunchKernelGGL((k_energy_pass<ST_F16, 0>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, sums);
+    if (storage == ST_F64) hipLaunchKernelGGL((k_energy_pass<ST_F64, 1>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    else if (storage == ST_F32) hipLaunchKernelGGL((k_energy_pass<ST_F32, 1>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    else hipLaunchKernelGGL((k_energy_pass<ST_F16, 1>), grid, block, 0, stream, layout, buf, g, lc, sums, partial);
+    hipLaunchKernelGGL(k_reduce_final_1, dim3(1), dim3(kBlock), 0, stream, partial, (int)blocks, out);
     return hipGetLastError();
 }
 

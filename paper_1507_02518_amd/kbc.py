@@ -103,6 +103,7 @@ def load():
         "kbc_moments": (ctypes.c_int, [_H, ctypes.c_void_p, ctypes.c_void_p]),
         "kbc_energy": (ctypes.c_int, [_H, _D]),
         "kbc_energy_series": (ctypes.c_int, [_H, ctypes.c_int64, _D]),
+        "kbc_energy_series_noalloc": (ctypes.c_int, [_H, ctypes.c_int64, _D]),
         "kbc_enstrophy": (ctypes.c_int, [_H, _D]),
         "kbc_statistics": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(kbc_stats)]),
         "kbc_gamma_statistics": (ctypes.c_int, [_H, ctypes.c_void_p]),
@@ -217,6 +218,16 @@ def kbc_energy_series(h: int, n: int) -> np.ndarray:
     k = np.zeros(max(int(n), 0), dtype=np.float64)
     _check(load().kbc_energy_series(h, int(n), k.ctypes.data_as(_D) if n > 0 else None),
            "kbc_energy_series")
+    return k
+
+
+NOALLOC_MAX_STEPS = 65536
+
+
+def kbc_energy_series_noalloc(h: int, n: int) -> np.ndarray:
+    k = np.zeros(max(int(n), 0), dtype=np.float64)
+    _check(load().kbc_energy_series_noalloc(h, int(n), k.ctypes.data_as(_D) if n > 0 else None),
+           "kbc_energy_series_noalloc")
     return k
 
 
