@@ -329,14 +329,18 @@ __host__ __device__ __forceinline__ double log1p_(double x)
     return log1p_series_ok(x) ? log1p_series(x) : log1p(x);
 }
 
-// 1/x from the hardware estimate refined by two Newton steps (to about one
-// ulp; x is a positive normal number here), in place of an IEEE division.
+// 1/x from the hardware estimate refined by Newton steps (x is a positive
+// normal number here), in place of an IEEE division: two steps take the
+// estimate (relative error near 2^-23) to about one ulp, one step to about
+// 2^-46.
+template <int STEPS = 2>
 __host__ __device__ __forceinline__ double rcp_refined_(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
+#pragma unroll
+    for (int k = 0; k < STEPS; ++k) r = fma(r, fma(-x, r, 1.0), r);
+    return r;
 #else
     return 1.0 / x;
 #endif
@@ -374,10 +378,15 @@ __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const d
         // 1 + x_i > 0  <=>  beta gamma hw_i < 1 + cc_i (hw_i has the sign of
         // dh_i; where it is 0 the population gives no bound); no branches, so
         // that the 27 terms stay one block of code
+        // The bound comes from a refined reciprocal (about one ulp) moved
+        // inward by 2^-50 of itself, so it never lies outside the exact one;
+        // the root is far inside (G runs to -inf / +inf at the ends).
         hmax = fmax(hmax, fabs(hw[i]));
-        const double b = (1.0 + cc[i]) / (beta * hw[i]);
-        hi = hw[i] > 0.0 ? fmin(hi, b) : hi;
-        lo = hw[i] < 0.0 ? fmax(lo, b) : lo;
+        const double ah = fabs(beta * hw[i]);
+        const double b = (1.0 + cc[i]) * rcp_refined_(ah);   // bound on +-gamma
+        const double shrink = fabs(b) * 0x1p-50;
+        hi = hw[i] > 0.0 ? fmin(hi, b - shrink) : hi;
+        lo = hw[i] < 0.0 ? fmax(lo, -b + shrink) : lo;
     }
     if (!(lo < hi) || !(lo > -inf) || !(hi < inf)) return false;
     double g = (g0 > lo && g0 < hi) ? g0 : 0.5 * (lo + hi);
@@ -395,7 +404,8 @@ __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const d
             const double x = cc[i] - bg * hw[i];
             series = series && log1p_series_ok(x);
             G += dh[i] * log1p_series(x);
-            const double hr = hw[i] * rcp_refined_(1.0 + x);
+            // G' and G'' only set the step length: one Newton refinement
+            const double hr = hw[i] * rcp_refined_<1>(1.0 + x);
             const double t = dh[i] * hr;
             D1 += t;
             D2 += t * hr;

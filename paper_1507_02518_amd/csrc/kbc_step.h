@@ -190,6 +190,13 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
         static_assert(SW == SW_AA_ODD, "aligned stores are for the odd AA sweep");
         // the 18 directions with v_x != 0 cross lanes: slot k = 2 (i / 3) +
         // (v_x > 0)
+        // The relaxed populations are pinned here, before any branch: the
+        // conditional stores below would otherwise let the compiler sink the
+        // last operations of the relaxation into them, where they no longer
+        // fuse as in the other sweeps and the pool kernel (a last-bit
+        // difference between a box alone and in the pool).
+#pragma unroll
+        for (int i = 0; i < 27; ++i) asm volatile("" : "+v"(f[i]));
         __shared__ T xch[18][kStepBlock];
         const uint32_t t = threadIdx.x, nb_ = blockDim.x;
         // directions with v_x = 0 stay in their lane and are stored at once

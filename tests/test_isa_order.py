@@ -120,3 +120,40 @@ def test_pool_kernels_load_everything_before_storing(asm):
         for b in blocks:
             text = "".join(b)
             assert "SL" not in text, (nm, text)
+
+
+_FP_OP = re.compile(r"^v_(fma|fmac|fmamk|fmaak|mul|add|sub|subrev|mac|ldexp|rcp|sqrt|div\w*|cvt\w*)_f(16|32|64)")
+
+
+def _fp_ops(asm, nm):
+    from collections import Counter
+
+    i = asm.index(nm + ":")
+    j = asm.index(".Lfunc_end", i)
+    ops = [ln.split()[0] for ln in asm[i:j].split("\n")
+           if ln.startswith("\t") and ln.strip() and _FP_OP.match(ln.split()[0])]
+    # fma, fmac (accumulating) and fmamk / fmaak (one literal operand) are the
+    # same fused operation
+    return Counter(re.sub(r"^v_(fmac|fmamk|fmaak)_", "v_fma_", op.replace("_e32", "").replace("_e64", ""))
+                   for op in ops)
+
+
+def test_every_sweep_and_the_pool_collide_with_the_same_arithmetic(asm):
+    """A box gives the same bits alone and in the pool, in pull and AA
+    streaming, only if every kernel evaluates the collision with the same
+    floating-point instructions (same contractions into FMAs): per storage
+    form and variant, the multiset of floating-point opcodes of the pull, AA
+    even and AA odd step kernels and of the pool's two sweeps is the same."""
+    names = re.findall(r"^(_ZN3kbc\S*(?:k_stepILi\dELi\dELi\dELb0|k_pool_stepILi\dELi\dELi\d)E\S*):",
+                       asm, flags=re.M)
+    groups = {}
+    for nm in names:
+        m = re.search(r"(k_step|k_pool_step)ILi(\d)ELi(\d)ELi(\d)", nm)
+        groups.setdefault((m.group(2), m.group(3)), []).append((nm, _fp_ops(asm, nm)))
+    assert len(groups) == 4 * 8
+    for key, lst in groups.items():
+        assert len(lst) == 5, (key, len(lst))
+        ref = lst[0][1]
+        assert sum(ref.values()) > 300, key
+        for nm, ops in lst[1:]:
+            assert ops == ref, (key, nm, ops - ref, ref - ops)
