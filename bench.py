@@ -84,6 +84,43 @@ def read_counters():
         return None
 
 
+VALU_COUNTS = os.path.join(ROOT, "profiles", "step_kernels_valu_256.txt")
+# VALU wave instructions the chip can issue per second: one per SIMD every
+# four cycles (a wave64 instruction occupies a 16-lane SIMD for four), 1024
+# SIMDs at 2.4 GHz
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+STORAGE_INDEX = {"F64": 0, "F32_DEV": 1, "F16_DEV": 2, "F32_DEV_X": 3}
+VARIANT_INDEX = {None: 3, "S_D": 0, "S_CDTQ": 7, "exact": 3}
+
+
+def read_valu_counts():
+    """VALU wave instructions per wave of each step kernel at 256^3 from the
+    committed rocprofv3 summary, or {} if it was taken on other sources."""
+    if not os.path.exists(VALU_COUNTS):
+        return {}
+    vals = {}
+    for line in open(VALU_COUNTS):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.rsplit("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.pop("kernel_source_digest", None) != kernel_source_digest():
+        return {}
+    return {k: float(v) for k, v in vals.items()}
+
+
+def valu_issue_ms(counts, storage, streaming, var, n):
+    """Time to issue the VALU instructions of one step (one wave per 64
+    nodes), from the measured counts: the kernel's VALU issue bound."""
+    gx = "true" if var == "exact" else "false"
+    sweeps = (0,) if streaming == "PULL" else (1, 2)
+    names = [f"k_step<{STORAGE_INDEX[storage]}, {VARIANT_INDEX[var]}, {sw}, {gx}>"
+             for sw in sweeps]
+    if not all(nm in counts for nm in names):
+        return None
+    per_wave = sum(counts[nm] for nm in names) / len(names)
+    return per_wave * (n ** 3 / 64) / VALU_ISSUE_PER_S * 1e3
+
+
 def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, variant=None,
               gamma=None, n=N, nu=NU):
     # the box enqueues on `stream` (a torch stream of default priority); the
@@ -387,16 +424,22 @@ def _select(spec, names):
 
 def run_forms(kbc, torch, u_dev, table, names, steps, warmup, stream, n, nu):
     out = {}
+    counts = read_valu_counts() if n == N else {}
     for name, dt, st, var in table:
         if name not in names:
             continue
         log(f"[bench] {n}^3 {name}")
         gamma = None
+        var_name = var
         if var == "exact":
             var, gamma = None, "exact"
         variant = getattr(kbc, var) if var else None
         r = time_form(kbc, torch, u_dev, getattr(kbc, dt), getattr(kbc, st), steps, warmup,
                       stream, variant, gamma, n=n, nu=nu)
+        t_valu = valu_issue_ms(counts, dt, st, var_name, n) if counts else None
+        if t_valu is not None:
+            r["valu_issue_ms"] = t_valu
+            r["frac_valu_roofline"] = t_valu / r["ms_per_step"]
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         log(f"[bench]   {r['mlups']:.0f} MLUPS, {r['algorithmic_GBs']:.0f} GB/s")
     return out
