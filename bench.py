@@ -252,7 +252,7 @@ def ensemble_and_serving(kbc, args):
 def precision_128(kbc, inputs, log):
     """128^3 decaying HIT (k0 = 4, u_rms = 0.04, nu = 5e-4, seed 1), 2000
     steps in each storage form: k(t) and Omega(t) every 10 steps against the
-    FP64 path and, where stored, the CPU checker's series."""
+    FP64 path and, where stored, the oracle's series."""
     golden = os.path.join(ROOT, "tests", "golden", "oracle_hit128_series.txt")
     ref = None
     if os.path.exists(golden):
@@ -336,8 +336,9 @@ def precision_512(kbc, inputs, log, steps=2000):
                                                 out["f64_aa"]["omega_final"] - 1)
         out[name]["spectrum_err_vs_f64"] = analysis.spectrum_error(spec[name], spec["f64_aa"])
         if e128 is not None:
-            out[name]["resolution_vs_oracle128_kappa_le_32"] = analysis.spectrum_error(
-                spec[name], e128, kmax=32)
+            out[name]["resolution_vs_oracle128_kappa_le_32"] = dict(
+                analysis.spectrum_error(spec[name], e128, kmax=32),
+                k_ratio=out[name]["k_final"] / float(e128.sum()))
     return out
 
 

@@ -118,8 +118,10 @@ def test_taylor_green_32_central_kbc_populations(orc, streaming):
 
 # Pull boxes are x-blocked: (96, 3, 2) in three chunks of 32 nodes, (192, 2, 1)
 # in three chunks of 64, the others in whole rows; AA boxes are in planes.
+# (64, 5, 3) has 960 nodes: its last workgroup of 256 threads ends past the
+# box by a whole wavefront.
 RAGGED = [(13, 7, 5), (1, 9, 4), (33, 17, 3), (2, 2, 2), (1, 1, 1), (70, 3, 2), (96, 3, 2),
-          (192, 2, 1)]
+          (192, 2, 1), (64, 5, 3)]
 
 
 @pytest.mark.parametrize("shape", RAGGED)
@@ -142,13 +144,15 @@ def test_ragged_boxes_all_variants(orc, shape, streaming):
 
 # Bounds: a wrong address gives errors of order 1e-2; these sit a few times
 # above the storage rounding of 7 steps at u up to 0.13.
-@pytest.mark.parametrize("shape", [(128, 4, 3), (96, 4, 3), (40, 3, 4)])
+@pytest.mark.parametrize("shape", [(128, 4, 3), (96, 4, 3), (40, 3, 4), (64, 5, 3)])
 @pytest.mark.parametrize("dtype,tol", [(kbc.F64, 1e-13), (kbc.F32_DEV, 1e-6),
                                        (kbc.F32_DEV_X, 3e-8), (kbc.F16_DEV, 1e-4)])
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
 def test_layouts_in_every_storage_form(orc, shape, dtype, tol, streaming):
     """Every storage form in both layouts: pull boxes x-blocked in chunks of
-    64 (nx = 128), 32 (nx = 96) or whole rows (nx = 40), AA boxes in planes;
+    64 (nx = 128, 64), 32 (nx = 96) or whole rows (nx = 40), AA boxes in
+    planes (64 x 5 x 3: a last workgroup that ends past the box, which the
+    line-aligned odd sweep must still take through its barrier);
     populations after 7 steps of a solenoidal start against the oracle."""
     u = inputs.hit(shape, 2.0, 0.04, seed=11)
     nu = 1e-3
@@ -181,13 +185,16 @@ def test_forced_gamma_paths(orc, gamma_kind):
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
 @pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
 def test_exact_entropic_gamma_matches_oracle(orc, streaming, variant):
-    """The exact stabilizer (root of Eq. result1 per node, Newton on the GPU,
-    bisection in the oracle): 16^3 Taylor-Green and a ragged box with a
-    density perturbation, 20 steps, element-wise; the run differs from the
-    estimate gamma* by far more than the tolerance."""
+    """The exact stabilizer (root of Eq. result1 per node, Halley's iteration
+    on the GPU, bisection in the oracle): 16^3 Taylor-Green and two boxes
+    with a density perturbation (13 x 7 x 5 and 64 x 3 x 2), 20 steps,
+    element-wise; the run differs from the estimate gamma* by far more than
+    the tolerance."""
     for shape, u, rho in [((16, 16, 16), inputs.taylor_green(16, 0.05), None),
                           ((13, 7, 5), inputs.smooth_random((13, 7, 5), 0.06, seed=3),
-                           inputs.random_density((13, 7, 5), 0.02, seed=3))]:
+                           inputs.random_density((13, 7, 5), 0.02, seed=3)),
+                          ((64, 3, 2), inputs.smooth_random((64, 3, 2), 0.06, seed=4),
+                           inputs.random_density((64, 3, 2), 0.02, seed=4))]:
         nu = 1e-3
         F = _oracle_run(orc, u, nu, 20, rho, variant=variant, exact=True)
         Fe = _oracle_run(orc, u, nu, 20, rho, variant=variant)

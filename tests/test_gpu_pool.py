@@ -81,7 +81,7 @@ def test_each_box_is_identical_alone_and_in_the_mix(dtype):
     batches of different lengths: every box equals its own solo run bit for
     bit."""
     specs = [((24, 24, 24), 4e-4, 31, 0), ((13, 17, 9), 1e-3, 18, 1), ((32, 32, 32), 2e-4, 25, 2),
-             ((10, 10, 10), 3e-3, 40, 3), ((7, 19, 5), 6e-4, 11, 4)]
+             ((10, 10, 10), 3e-3, 40, 3), ((7, 19, 5), 6e-4, 11, 4), ((64, 5, 3), 8e-4, 14, 5)]
     fields = [inputs.hit(s, 3.0, 0.04, seed=seed) for s, _, _, seed in specs]
     budget = sum(_pop_bytes(s, dtype) for s, _, _, _ in specs) + (16 << 20)
     got = {}
@@ -95,6 +95,8 @@ def test_each_box_is_identical_alone_and_in_the_mix(dtype):
         slot[3] = pool.admit(fields[3], specs[3][1], specs[3][2])
         pool.advance(5)
         slot[4] = pool.admit(fields[4], specs[4][1], specs[4][2])
+        pool.advance(1)
+        slot[5] = pool.admit(fields[5], specs[5][1], specs[5][2])
         for g in (2, 7, 1, 9, 9, 9, 9):
             pool.advance(g)
         pool.sync()
