@@ -233,6 +233,47 @@ def test_checkpoint_restart_is_bitwise(streaming, dtype, shape):
     assert np.array_equal(fa, fb)
 
 
+# ---------------------------------------------------- degenerate cases ----
+
+@pytest.mark.parametrize("dtype", [kbc.F64, kbc.F32_DEV, kbc.F32_DEV_X, kbc.F16_DEV])
+@pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
+def test_fluid_at_rest_stays_at_rest(orc, dtype, streaming):
+    """rho = 1, u = 0 is a fixed point of the step (f = f^eq = W, ds = dh = 0,
+    the stabilizer takes its fallback): the deviation forms store exactly 0
+    and stay bitwise at rest; FP64 stays within a few ulp of W (the
+    equilibrium is rebuilt from summed moments every step)."""
+    shape = (12, 7, 5)
+    with _box(shape, 1e-3, dtype, streaming=streaming) as b:
+        b.init_velocity(np.zeros((3,) + shape[::-1]))
+        f0 = b.populations()
+        b.step(9)
+        f9 = b.populations()
+        rho, u = b.moments()
+    W = orc.init_feq(np.zeros((3,) + shape[::-1]))
+    assert np.abs(f0 - W).max() <= 4e-16
+    if dtype == kbc.F64:
+        assert np.abs(f9 - W).max() <= 4e-16
+    else:
+        assert np.array_equal(f9, f0)
+    assert np.abs(u).max() <= 1e-16 and np.abs(rho - 1.0).max() <= 1e-15
+
+
+def test_equilibrium_start_takes_the_fallback_gamma():
+    """At t = 0 the populations are the equilibrium of their own moments, so
+    <dh|dh> vanishes to rounding at every node and the stabilizer takes
+    gamma = 2 everywhere (as the oracle does, pinned on the CPU); one step
+    later the field is off equilibrium and gamma spreads."""
+    with _box((16, 16, 16), 1e-3) as b:
+        b.init_velocity(inputs.taylor_green(16, 0.05))
+        g0 = b.gamma_statistics()
+        b.step(1)
+        g1 = b.gamma_statistics()
+    say(f"gamma at t=0: mean {g0['mean']} std {g0['std']}; t=1: mean {g1['mean']:.6f} "
+        f"std {g1['std']:.3e}")
+    assert g0["mean"] == 2.0 and g0["std"] == 0.0 and g0["min"] == g0["max"] == 2.0
+    assert g1["std"] > 0.0
+
+
 def test_runs_are_deterministic():
     u = inputs.hit(24, 4.0, 0.04, seed=5)
     out = []
