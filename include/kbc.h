@@ -80,8 +80,10 @@ typedef enum { KBC_PULL = 0, KBC_AA = 1 } kbc_streaming;
  * of Eq. result21 (the paper's scheme).  KBC_GAMMA_FIXED: gamma =
  * gamma_value everywhere (2 = LBGK, 1/beta = regularised LB).
  * KBC_GAMMA_EXACT: the root of the entropy-maximum condition Eq. result1 at
- * every node, found by safeguarded Newton iteration from gamma* in FP64
- * (about 3-6 iterations of 27 logarithms per node: an ALU-bound kernel);
+ * every node, found in FP64 from gamma* by solving a fourth-order
+ * expansion of the condition about it (one pass of 27 logarithms at almost
+ * every node; safeguarded Halley iteration where the expansion is not
+ * accurate enough: an ALU-bound kernel);
  * gamma = 2 where <dh|dh> <= gamma_eps rho or where the condition has no
  * root with all post-collision populations positive.  Single boxes only;
  * kbc_pool_create rejects it. */

@@ -360,23 +360,29 @@ __host__ __device__ __forceinline__ double rcp_refined_(double x)
 //   G(gamma) = sum_i dh_i ln(1 + x_i),  x_i = ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / f^eq_i,
 // where 1 + x_i = f'_i / f^eq_i.  The caller passes, per population, dh_i,
 // hw_i = dh_i / f^eq_i and cc_i = (dh_i - (2 beta - 1) ds_i) / f^eq_i, so that
-// x_i = cc_i - beta gamma hw_i.  With r_i = 1 / (1 + x_i),
-//   G'  = -beta   sum_i dh_i hw_i r_i           = -beta D1,
-//   G'' = -beta^2 sum_i dh_i (hw_i r_i)^2       = -beta^2 D2.
-// On the interval where all 1 + x_i are positive G falls strictly (D1 > 0),
-// so the root there is unique.  Halley's iteration from the estimate g0,
-// step = 2 G D1 / (beta (2 D1^2 + G D2)) (Newton's G / (beta D1) where
-// |G D2| > D1^2), each iterate kept inside a bracket that shrinks with the
-// sign of G (a step that leaves it is replaced by bisection); FP64 for every
-// storage form.  A change dg of gamma moves f'_i by beta dg dh_i, so the
-// iteration stops once the last correction moves no population by more than
-// 1e-16 f^eq_i: further digits of gamma cannot change the result, and where
-// dh << ds they are not determined by G to begin with.  Two steps in a row
-// bound the next one (at least quadratic convergence: s_{n+1} <~ s_n^3 /
-// s_{n-1}^2), and when that bound is already below the tolerance the
-// iteration stops without evaluating G again.  From gamma* (first-order
-// accurate) this takes two evaluations on resolved flows.  Returns false,
-// leaving gamma to the caller, when no bracket exists.
+// x_i = cc_i - beta gamma hw_i.  With r_i = hw_i / (1 + x_i) and
+// M_k = sum_i dh_i r_i^k,
+//   G'  = -beta   M_1,   G'' = -beta^2 M_2,
+// and, exactly, G(gamma + d) = G(gamma) - sum_{k>=1} (beta d)^k M_k / k.
+// On the interval where all 1 + x_i are positive G falls strictly (M_1 > 0),
+// so the root there is unique.  Each pass over the populations (from the
+// estimate g0 first) forms G and M_1..M_4 and solves the expansion cut after
+// k = 4 for d by Newton's method from Halley's step; with q = |beta d| max r_i
+// the dropped terms move that root by at most |d| q^4 / (5 (1 - q)), and when
+// that is below the tolerance the pass ends the search.  Otherwise Halley's
+// step 2 G M_1 / (beta (2 M_1^2 + G M_2)) (Newton's G / (beta M_1) where
+// |G M_2| > M_1^2) is taken and the pass repeated, each iterate kept inside
+// a bracket that shrinks with the sign of G (a step that leaves it is
+// replaced by bisection); FP64 for every storage form.  A change dg of gamma
+// moves f'_i by beta dg dh_i, so the search stops once the last correction
+// moves no population by more than 1e-16 f^eq_i: further digits of gamma
+// cannot change the result, and where dh << ds they are not determined by G
+// to begin with.  Two Halley steps in a row bound the next one (at least
+// quadratic convergence: s_{n+1} <~ s_n^3 / s_{n-1}^2), and when that bound
+// is already below the tolerance the search stops without evaluating G
+// again.  From gamma* (first-order accurate) one pass suffices at almost
+// every node.  Returns false, leaving gamma to the caller, when no bracket
+// exists.
 __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const double (&hw)[27],
                                                  const double (&cc)[27], double beta, double g0,
                                                  double& gamma)
@@ -406,8 +412,10 @@ __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const d
     for (int it = 0; it < 80; ++it) {
         // G by the series wherever it holds (no branch per population: one
         // block of straight code); a node with some |x_i| >= 1/16 sums G
-        // again with the library logarithm
-        double G = 0.0, D1 = 0.0, D2 = 0.0;
+        // again with the library logarithm.  With r_i = hw_i / (1 + x_i) the
+        // same pass forms M_k = sum_i dh_i r_i^k, k = 1..4 (each term of M_1
+        // is dh_i^2 / (f^eq_i (1 + x_i)) >= 0, so |M_k| <= rmax^(k-1) M_1).
+        double G = 0.0, M1 = 0.0, M2 = 0.0, M3 = 0.0, M4 = 0.0, rmax = 0.0;
         bool series = true;
         const double bg = beta * g;
 #pragma unroll
@@ -415,20 +423,47 @@ __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const d
             const double x = cc[i] - bg * hw[i];
             series = series && log1p_series_ok(x);
             G += dh[i] * log1p_series(x);
-            // G' and G'' only set the step length: one Newton refinement
-            const double hr = hw[i] * rcp_refined_<1>(1.0 + x);
-            const double t = dh[i] * hr;
-            D1 += t;
-            D2 += t * hr;
+            const double r = hw[i] * rcp_refined_(1.0 + x);
+            const double t1 = dh[i] * r, t2 = t1 * r, t3 = t2 * r;
+            M1 += t1;
+            M2 += t2;
+            M3 += t3;
+            M4 += t3 * r;
+            rmax = fmax(rmax, fabs(r));
         }
         if (!series) {
             G = 0.0;
 #pragma unroll
             for (int i = 0; i < 27; ++i) G += dh[i] * log1p_(cc[i] - bg * hw[i]);
         }
-        const double GD2 = G * D2, D1s = D1 * D1;
-        const double step = fabs(GD2) <= D1s ? 2.0 * G * D1 / (beta * (2.0 * D1s + GD2))
-                                             : G / (beta * D1);
+        if (G == 0.0) break;
+        if (G > 0.0) lo = g;
+        else hi = g;
+        // Halley's step from G, G' = -beta M1, G'' = -beta^2 M2
+        const double GD2 = G * M2, D1s = M1 * M1;
+        const double step = fabs(GD2) <= D1s ? 2.0 * G * M1 / (beta * (2.0 * D1s + GD2))
+                                             : G / (beta * M1);
+        // About g, ln(1 + x_i - beta d hw_i) = ln(1 + x_i) + ln(1 - beta d r_i),
+        // so G(g + d) = G - sum_k (beta d)^k M_k / k.  The root d of the
+        // expansion to k = 4 (Newton from Halley's step) is the root of G to
+        // within |d| q^4 / (5 (1 - q)), q = |beta d| rmax; where that is below
+        // the tolerance one pass over the populations has found gamma.
+        double d = step;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double y = beta * d;
+            const double P = G - y * (M1 + y * (0.5 * M2 + y * ((1.0 / 3.0) * M3 + 0.25 * y * M4)));
+            const double dP = -beta * (M1 + y * (M2 + y * (M3 + y * M4)));
+            d -= P / dP;
+        }
+        const double q = fabs(beta * d) * rmax, q2 = q * q;
+        if (q < 0.25 && fabs(d) * q2 * q2 <= 4.0 * dg_tol * (1.0 - q)) {
+            const double gn = g + d;
+            if (gn > lo && gn < hi) {
+                g = gn;
+                break;
+            }
+        }
         const double as = fabs(step);
         if (as <= dg_tol ||                      // converged (also when the step
             (prev > 0.0 && as < prev &&          // is below one ulp of g), or
@@ -436,8 +471,6 @@ __host__ __device__ inline bool gamma_exact_root(const double (&dh)[27], const d
             g += step;
             break;
         }
-        if (G > 0.0) lo = g;
-        else hi = g;
         double gn = g + step;
         if (!(gn > lo && gn < hi)) {
             gn = 0.5 * (lo + hi);

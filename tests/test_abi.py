@@ -187,7 +187,7 @@ def test_device_collision_built_for_the_host_matches_the_oracle(orc):
     against the oracle's collision for all eight variants, natural and
     central: FP64 within 5e-15, FP32 deviation storage with FP64-formed
     non-equilibrium within 3e-8 (measured 1.7e-15 and 7e-9), and the exact
-    stabilizer (Newton on Eq. result1) against the oracle's bisection within
+    stabilizer (root of Eq. result1) against the oracle's bisection within
     5e-15 (measured 1.7e-15; the exact and estimated gamma differ by ~3e-3)."""
     clang = "/opt/rocm/llvm/bin/clang++"
     if not os.path.exists(clang):

@@ -185,8 +185,9 @@ def test_forced_gamma_paths(orc, gamma_kind):
 @pytest.mark.parametrize("streaming", [kbc.PULL, kbc.AA])
 @pytest.mark.parametrize("variant", [kbc.S_DTQ, kbc.S_CDTQ])
 def test_exact_entropic_gamma_matches_oracle(orc, streaming, variant):
-    """The exact stabilizer (root of Eq. result1 per node, Halley's iteration
-    on the GPU, bisection in the oracle): 16^3 Taylor-Green and two boxes
+    """The exact stabilizer (root of Eq. result1 per node, from an expansion
+    about gamma* with Halley's iteration as fallback on the GPU, bisection in
+    the oracle): 16^3 Taylor-Green and two boxes
     with a density perturbation (13 x 7 x 5 and 64 x 3 x 2), 20 steps,
     element-wise; the run differs from the estimate gamma* by far more than
     the tolerance."""
