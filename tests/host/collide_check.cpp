@@ -2,7 +2,8 @@
 // here for the CPU) against the oracle's seven-step collision, for the four
 // natural and the four central-moment variants: FP64 storage, FP32 deviation
 // storage with the FP64-formed non-equilibrium, and FP64 with the exact
-// stabilizer (root of Eq. result1) against the oracle's bisection.  Prints
+// stabilizer (root of Eq. result1) against the oracle's bisection, near and
+// far from equilibrium.  Prints
 // the largest differences and exits non-zero past the bounds given on the
 // command line.
 #include <cmath>
@@ -87,9 +88,46 @@ int main(int argc, char** argv)
                 ex = std::fmax(ex, std::fabs(fx[i] - PX[i]));
             }
         }
-        const bool ok = e64 <= tol64 && e32 <= tol32 && ex <= tolx;
-        std::printf("variant %d: max|dP| FP64 %.3e  FP32-dev-X %.3e  FP64 exact gamma %.3e  %s\n",
-                    v, e64, e32, ex, ok ? "ok" : "FAIL");
+        // the exact stabilizer far from equilibrium (perturbations of 10-30%),
+        // where the start gamma* can lie outside the interval of positive
+        // post-collision populations and the root takes several passes.  There
+        // the root moves with the rounding of G (terms dh_i ln(1 + x_i) with
+        // |x_i| up to ~1 that cancel), so the bound is 40x the near one.
+        double exf = 0.0;
+        for (int trial = 0; trial < 400; ++trial) {
+            const double nu = trial % 2 ? 1e-4 : 5e-3;
+            const double beta = kbco_beta_from_nu(nu);
+            const double u[3] = {uu(rng), uu(rng), uu(rng)};
+            double F[27];
+            kbco_feq(rr(rng), u, F);
+            const double amp = 0.1 + 0.2 * (trial % 3) / 2.0;
+            for (int i = 0; i < 27; ++i) F[i] *= std::exp(amp * nn(rng));
+            double PX[27];
+            kbco_collide(F, beta, v, KBCO_GAMMA_EXACT, 0.0, 1e-28, PX, nullptr, nullptr, nullptr);
+            kbc::Coll c{};
+            c.beta = beta;
+            c.inv_beta = 1.0 / beta;
+            c.c2 = 2.0 - 1.0 / beta;
+            c.gamma_fixed = 0;
+            c.gamma_eps = 1e-28;
+            double fx[27];
+            for (int i = 0; i < 27; ++i) fx[i] = F[i];
+            switch (v) {
+            case 0: kbc::collide<kbc::ST_F64, 0, true>(fx, c); break;
+            case 1: kbc::collide<kbc::ST_F64, 1, true>(fx, c); break;
+            case 2: kbc::collide<kbc::ST_F64, 2, true>(fx, c); break;
+            case 3: kbc::collide<kbc::ST_F64, 3, true>(fx, c); break;
+            case 4: kbc::collide<kbc::ST_F64, 4, true>(fx, c); break;
+            case 5: kbc::collide<kbc::ST_F64, 5, true>(fx, c); break;
+            case 6: kbc::collide<kbc::ST_F64, 6, true>(fx, c); break;
+            default: kbc::collide<kbc::ST_F64, 7, true>(fx, c); break;
+            }
+            for (int i = 0; i < 27; ++i) exf = std::fmax(exf, std::fabs(fx[i] - PX[i]));
+        }
+        const bool ok = e64 <= tol64 && e32 <= tol32 && ex <= tolx && exf <= 40.0 * tolx;
+        std::printf("variant %d: max|dP| FP64 %.3e  FP32-dev-X %.3e  FP64 exact gamma %.3e "
+                    "(far from equilibrium %.3e)  %s\n",
+                    v, e64, e32, ex, exf, ok ? "ok" : "FAIL");
         if (!ok) ++fails;
     }
     return fails ? 1 : 0;
