@@ -4,7 +4,7 @@
  * "Entropic multi-relaxation lattice Boltzmann scheme for turbulent flows"
  * (arXiv:1507.02518).
  *
- * TEST INFRASTRUCTURE ONLY: this file is the checker of the GPU library.
+ * TEST INFRASTRUCTURE ONLY: this file is the oracle the GPU library is tested against.
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark load it; the GPU library never does, and the two share no code.
  *

@@ -2,7 +2,7 @@
 
 This module holds no arithmetic of the lattice Boltzmann method itself; it
 only builds velocity fields u[3][nz][ny][nx] (float64, x fastest) that both
-the GPU path and its CPU checker start from.
+the GPU path and its CPU oracle start from.
 
 * ``taylor_green``: u = (U sin x cos y cos z, -U cos x sin y cos z, 0) with
   node coordinates x_j = 2 pi j / N (no half-cell offset).

@@ -187,9 +187,9 @@ def test_shear_wave_is_carried_by_a_uniform_flow(orc):
     assert shift == pytest.approx(V * steps, rel=2e-3)
 
 
-def test_host_spectrum_matches_the_checker(orc):
+def test_host_spectrum_matches_the_oracle(orc):
     """The package's host spectrum (real FFT, half spectrum) equals the
-    checker's full-FFT spectrum shell by shell."""
+    oracle's full-FFT spectrum shell by shell."""
     from paper_1507_02518_amd import analysis
 
     for shape in [(16, 16, 16), (15, 12, 10), (24, 24, 24)]:
