@@ -195,8 +195,10 @@ struct LoadCtx {
 using PoolFn = void (*)(const PoolBox*, const uint32_t*, const PoolMeta*, int);
 using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
 
+// c64: the box is x-blocked in chunks of 64 nodes (a pull sweep may then
+// take a kernel with that geometry compiled in)
 template <int S, bool GX>
-StepFn step_kernel(int variant, int sweep);
+StepFn step_kernel(int variant, int sweep, bool c64);
 template <int S>
 PoolFn pool_kernel(int variant, int sweep);   // estimate gamma only
 template <int S, bool GX>

@@ -542,11 +542,13 @@ hipError_t step_launch_shape(int storage, int variant, int sweep, bool exact_gam
 {
     // the AA kernels address populations in planes (see node_update)
     if (sweep != SW_PULL && !geom_is_planes(g)) return hipErrorInvalidValue;
+    // x-blocked in chunks of 64 nodes (geom_blocked)
+    const bool c64 = g.xshift == 6 && g.xmask == 63 && g.plane == 64 && g.chunk == 27 * 64;
     switch (storage) {
-    case ST_F64: *fn = exact_gamma ? step_kernel<ST_F64, true>(variant, sweep) : step_kernel<ST_F64, false>(variant, sweep); break;
-    case ST_F32: *fn = exact_gamma ? step_kernel<ST_F32, true>(variant, sweep) : step_kernel<ST_F32, false>(variant, sweep); break;
-    case ST_F32X: *fn = exact_gamma ? step_kernel<ST_F32X, true>(variant, sweep) : step_kernel<ST_F32X, false>(variant, sweep); break;
-    default: *fn = exact_gamma ? step_kernel<ST_F16, true>(variant, sweep) : step_kernel<ST_F16, false>(variant, sweep); break;
+    case ST_F64: *fn = exact_gamma ? step_kernel<ST_F64, true>(variant, sweep, c64) : step_kernel<ST_F64, false>(variant, sweep, c64); break;
+    case ST_F32: *fn = exact_gamma ? step_kernel<ST_F32, true>(variant, sweep, c64) : step_kernel<ST_F32, false>(variant, sweep, c64); break;
+    case ST_F32X: *fn = exact_gamma ? step_kernel<ST_F32X, true>(variant, sweep, c64) : step_kernel<ST_F32X, false>(variant, sweep, c64); break;
+    default: *fn = exact_gamma ? step_kernel<ST_F16, true>(variant, sweep, c64) : step_kernel<ST_F16, false>(variant, sweep, c64); break;
     }
     // One wavefront per workgroup for the exact stabilizer (one wave per
     // SIMD: 64-thread workgroups fill the CUs more evenly; at 256^3 the pull

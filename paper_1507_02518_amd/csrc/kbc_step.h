@@ -78,7 +78,13 @@ typedef __attribute__((address_space(1))) char gchar_t;
 // node of the workgroup's contiguous range of blockDim.x nodes; `store`:
 // whether this thread's node is real (a thread past the last node takes the
 // last node's inputs, so its LDS entries are defined, and stores nothing).
-template <int S, int V, int SW, bool GX = false, bool ALN = false>
+//
+// C64 (pull sweep of a box x-blocked in chunks of 64 nodes): the chunk
+// geometry is a compile-time constant, so the 27 directions of a chunk lie
+// at fixed byte distances that the loads and stores carry in their
+// immediate offset field where it reaches (FP16: all 27, 128 bytes apart)
+// instead of one scalar base per direction.
+template <int S, int V, int SW, bool GX = false, bool ALN = false, bool C64 = false>
 __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const Geom& g,
                                             const Coll& c, const int8_t* sexp, uint32_t n,
                                             uint32_t n0 = 0, bool store = true)
@@ -95,7 +101,8 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     // Pull boxes may be x-blocked (see Geom); AA boxes are always laid out
     // in planes, where the offset of x in its row is x itself.
     auto xoff = [&](uint32_t xx) -> uint32_t {
-        if constexpr (SW == SW_PULL) return (xx >> g.xshift) * (g.chunk * EB) + (xx & g.xmask) * EB;
+        if constexpr (C64) return (xx >> 6) * (27 * 64 * EB) + (xx & 63) * EB;
+        else if constexpr (SW == SW_PULL) return (xx >> g.xshift) * (g.chunk * EB) + (xx & g.xmask) * EB;
         else return xx * EB;
     };
     const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
@@ -114,7 +121,7 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
     // through scalar plane bases, in the odd FP16 sweep it schedules worse.)
     const char* src = static_cast<const char*>(srcv);
     char* dst = static_cast<char*>(dstv);
-    const uint64_t planeb = g.plane * EB;
+    const uint64_t planeb = C64 ? 64 * EB : g.plane * EB;
     // Where every plane is accessed at the same offset (the loads and stores
     // of the even AA sweep, the stores of the pull sweep) the compiler would
     // fold buffer + offset into one 64-bit vector address and add each
@@ -270,10 +277,11 @@ __device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, bool e
 
 // Fused step of one box: one thread per node, workgroups of up to
 // kStepBlock threads (the launch picks the size).  GX: exact stabilizer.
+// C64: pull sweep on 64-node chunks (node_update).
 #ifndef KBC_GX_WAVES_PER_EU
 #define KBC_GX_WAVES_PER_EU 1
 #endif
-template <int S, int V, int SW, bool GX>
+template <int S, int V, int SW, bool GX, bool C64 = false>
 __global__ void __launch_bounds__(kStepBlock)
 #if KBC_WAVES_PER_EU
 __attribute__((amdgpu_waves_per_eu(KBC_WAVES_PER_EU, 8)))
@@ -295,7 +303,7 @@ k_step(StepParams p)
                                         real ? n : p.g.nnodes - 1, n0, real);
     } else {
         if (n >= p.g.nnodes) return;
-        node_update<S, V, SW, GX>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
+        node_update<S, V, SW, GX, false, C64>(p.src, p.dst, p.g, p.c, p.scale_exp, n);
     }
 }
 

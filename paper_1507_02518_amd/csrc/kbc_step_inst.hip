@@ -15,12 +15,22 @@ namespace {
 constexpr int kS = KBC_INST_STORAGE;
 constexpr bool kGX = KBC_INST_EXACT != 0;
 
+// The pull sweep on 64-node chunks with the chunk geometry compiled in is
+// instantiated for FP16 storage, where it removes the scalar-register spills
+// of the per-direction bases (4.7% faster at 256^3; the other forms measured
+// the same either way).
+constexpr bool kC64 = kS == ST_F16;
+
 template <int V>
-StepFn step_of_sweep(int sw)
+StepFn step_of_sweep(int sw, bool c64)
 {
-    return sw == SW_PULL ? k_step<kS, V, SW_PULL, kGX>
-                         : (sw == SW_AA_EVEN ? k_step<kS, V, SW_AA_EVEN, kGX>
-                                             : k_step<kS, V, SW_AA_ODD, kGX>);
+    if (sw == SW_PULL) {
+        if constexpr (kC64) {
+            if (c64) return k_step<kS, V, SW_PULL, kGX, true>;
+        }
+        return k_step<kS, V, SW_PULL, kGX>;
+    }
+    return sw == SW_AA_EVEN ? k_step<kS, V, SW_AA_EVEN, kGX> : k_step<kS, V, SW_AA_ODD, kGX>;
 }
 
 template <int V>
@@ -32,18 +42,18 @@ PoolFn pool_of_sweep(int sw)
 }  // namespace
 
 template <int S, bool GX>
-StepFn step_kernel(int v, int sw)
+StepFn step_kernel(int v, int sw, bool c64)
 {
     static_assert(S == kS && GX == kGX, "instantiated for one storage form and mode only");
     switch (v) {
-    case V_D: return step_of_sweep<V_D>(sw);
-    case V_DT: return step_of_sweep<V_DT>(sw);
-    case V_DQ: return step_of_sweep<V_DQ>(sw);
-    case V_CD: return step_of_sweep<V_CD>(sw);
-    case V_CDT: return step_of_sweep<V_CDT>(sw);
-    case V_CDQ: return step_of_sweep<V_CDQ>(sw);
-    case V_CDTQ: return step_of_sweep<V_CDTQ>(sw);
-    default: return step_of_sweep<V_DTQ>(sw);
+    case V_D: return step_of_sweep<V_D>(sw, c64);
+    case V_DT: return step_of_sweep<V_DT>(sw, c64);
+    case V_DQ: return step_of_sweep<V_DQ>(sw, c64);
+    case V_CD: return step_of_sweep<V_CD>(sw, c64);
+    case V_CDT: return step_of_sweep<V_CDT>(sw, c64);
+    case V_CDQ: return step_of_sweep<V_CDQ>(sw, c64);
+    case V_CDTQ: return step_of_sweep<V_CDTQ>(sw, c64);
+    default: return step_of_sweep<V_DTQ>(sw, c64);
     }
 }
 
@@ -63,7 +73,7 @@ GammaFn gamma_kernel(int v)
     }
 }
 
-template StepFn step_kernel<kS, kGX>(int, int);
+template StepFn step_kernel<kS, kGX>(int, int, bool);
 template GammaFn gamma_kernel<kS, kGX>(int);
 
 #if !KBC_INST_EXACT

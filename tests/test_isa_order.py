@@ -143,7 +143,8 @@ def test_every_sweep_and_the_pool_collide_with_the_same_arithmetic(asm):
     streaming, only if every kernel evaluates the collision with the same
     floating-point instructions (same contractions into FMAs): per storage
     form and variant, the multiset of floating-point opcodes of the pull, AA
-    even and AA odd step kernels and of the pool's two sweeps is the same."""
+    even and AA odd step kernels (FP16 also the pull sweep on 64-node chunks)
+    and of the pool's two sweeps is the same."""
     names = re.findall(r"^(_ZN3kbc\S*(?:k_stepILi\dELi\dELi\dELb0|k_pool_stepILi\dELi\dELi\d)E\S*):",
                        asm, flags=re.M)
     groups = {}
@@ -152,7 +153,8 @@ def test_every_sweep_and_the_pool_collide_with_the_same_arithmetic(asm):
         groups.setdefault((m.group(2), m.group(3)), []).append((nm, _fp_ops(asm, nm)))
     assert len(groups) == 4 * 8
     for key, lst in groups.items():
-        assert len(lst) == 5, (key, len(lst))
+        # FP16 (storage 2) adds the pull sweep on 64-node chunks
+        assert len(lst) == (6 if key[0] == "2" else 5), (key, len(lst))
         ref = lst[0][1]
         assert sum(ref.values()) > 300, key
         for nm, ops in lst[1:]:
