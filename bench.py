@@ -113,8 +113,11 @@ def valu_issue_ms(counts, storage, streaming, var, n):
     nodes), from the measured counts: the kernel's VALU issue bound."""
     gx = "true" if var == "exact" else "false"
     sweeps = (0,) if streaming == "PULL" else (1, 2)
-    names = [f"k_step<{STORAGE_INDEX[storage]}, {VARIANT_INDEX[var]}, {sw}, {gx}>"
-             for sw in sweeps]
+    # FP16 pull boxes in 64-node chunks run the kernel with that geometry
+    # compiled in
+    c64 = "true" if storage == "F16_DEV" and streaming == "PULL" and n % 64 == 0 and n > 64 else "false"
+    names = [f"k_step<{STORAGE_INDEX[storage]}, {VARIANT_INDEX[var]}, {sw}, {gx}, "
+             f"{c64 if sw == 0 else 'false'}>" for sw in sweeps]
     if not all(nm in counts for nm in names):
         return None
     per_wave = sum(counts[nm] for nm in names) / len(names)
@@ -215,14 +218,14 @@ def ensemble_and_serving(kbc, args):
             log(f"[bench]   {name}: p50 {r['p50_s']:.2f}s p99 {r['p99_s']:.2f}s {r['mlups']:.0f} MLUPS")
 
         # policies: "aged" shortest remaining work first with aging (weight
-        # 0.3, batches of >= 4M nodes), the default; "srpt" the same without
-        # aging in batches of >= 8M nodes (best median); "loop" first come
-        # first served, one box at a time
+        # 0.3, batches of >= 4M nodes and 50 steps), the default; "srpt" the
+        # same without aging in batches of >= 8M nodes and 25 steps (best
+        # median); "loop" first come first served, one box at a time
         runs = {}
         for rep in range(args.serve_reps):
             for pol in args.serve_policies.split(","):
                 if pol == "aged":
-                    r = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25,
+                    r = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=50,
                                           tune_cache=cache, min_nodes=4 << 20, age_weight=0.3)
                 elif pol == "srpt":
                     r = serve.run_serving(trace, kbc.F32_DEV_X, budget=200 << 30, g=25,
@@ -237,7 +240,7 @@ def ensemble_and_serving(kbc, args):
         same = all(rr["results"][i] == first["results"][i]
                    for rs in runs.values() for rr in rs for i in first["results"])
         names = {"aged": ("pool_aged", "shortest remaining work first with aging (weight 0.3), "
-                                       "batches >= 4M nodes"),
+                                       "batches >= 4M nodes of 50 steps"),
                  "srpt": ("pool", "shortest remaining work first, batches >= 8M nodes"),
                  "loop": ("loop", "first come first served, one box at a time")}
         out["serving"] = {"requests": len(trace), "rate_per_s": 20.0, "storage": "f32dev_x",
