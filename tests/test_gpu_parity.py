@@ -187,15 +187,17 @@ def test_forced_gamma_paths(orc, gamma_kind):
 def test_exact_entropic_gamma_matches_oracle(orc, streaming, variant):
     """The exact stabilizer (root of Eq. result1 per node, from an expansion
     about gamma* with Halley's iteration as fallback on the GPU, bisection in
-    the oracle): 16^3 Taylor-Green and two boxes
-    with a density perturbation (13 x 7 x 5 and 64 x 3 x 2), 20 steps,
-    element-wise; the run differs from the estimate gamma* by far more than
-    the tolerance."""
+    the oracle): 16^3 Taylor-Green and three boxes with a density
+    perturbation (13 x 7 x 5, 64 x 3 x 2, and 128 x 4 x 3, whose pull sweep
+    runs on 64-node chunks), 20 steps, element-wise; the run differs from the
+    estimate gamma* by far more than the tolerance."""
     for shape, u, rho in [((16, 16, 16), inputs.taylor_green(16, 0.05), None),
                           ((13, 7, 5), inputs.smooth_random((13, 7, 5), 0.06, seed=3),
                            inputs.random_density((13, 7, 5), 0.02, seed=3)),
                           ((64, 3, 2), inputs.smooth_random((64, 3, 2), 0.06, seed=4),
-                           inputs.random_density((64, 3, 2), 0.02, seed=4))]:
+                           inputs.random_density((64, 3, 2), 0.02, seed=4)),
+                          ((128, 4, 3), inputs.smooth_random((128, 4, 3), 0.06, seed=5),
+                           inputs.random_density((128, 4, 3), 0.02, seed=5))]:
         nu = 1e-3
         F = _oracle_run(orc, u, nu, 20, rho, variant=variant, exact=True)
         Fe = _oracle_run(orc, u, nu, 20, rho, variant=variant)
