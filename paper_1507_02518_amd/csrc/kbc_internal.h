@@ -179,9 +179,11 @@ constexpr int kPoolMaxBlock = 512;
 // Persistent grid-stride loop over the group's tiles; block <= 512.
 // boxes and tstart are the whole table (tstart[b] = boxes[b].tile0, a
 // compact copy for the tile -> box search); meta is the group's entry.
+// one: the launch has a block for every tile of the group and one run of
+// nodes per tile (sub = 1), so the single-tile kernel applies
 hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
                             const uint32_t* tstart, const PoolMeta* meta, int k, int block,
-                            int grid, hipStream_t stream);
+                            int grid, bool one, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Kernel tables.  The step, pool and stabilizer-statistics kernels are
@@ -200,7 +202,7 @@ using GammaFn = void (*)(int, const void*, Geom, Coll, LoadCtx, double*);
 template <int S, bool GX>
 StepFn step_kernel(int variant, int sweep, bool c64);
 template <int S>
-PoolFn pool_kernel(int variant, int sweep);   // estimate gamma only
+PoolFn pool_kernel(int variant, int sweep, bool one);   // estimate gamma only
 template <int S, bool GX>
 GammaFn gamma_kernel(int variant);
 

@@ -574,16 +574,16 @@ hipError_t launch_step(int storage, int variant, int sweep, bool exact_gamma, co
 
 hipError_t launch_pool_step(int storage, int variant, int sweep, const PoolBox* boxes,
                             const uint32_t* tstart, const PoolMeta* meta, int k, int block,
-                            int grid, hipStream_t stream)
+                            int grid, bool one, hipStream_t stream)
 {
     if (block < 64 || block > kPoolMaxBlock || block % 64 || grid < 1) return hipErrorInvalidValue;
     if (sweep != SW_AA_EVEN && sweep != SW_AA_ODD) return hipErrorInvalidValue;
     PoolFn fn;
     switch (storage) {
-    case ST_F64: fn = pool_kernel<ST_F64>(variant, sweep); break;
-    case ST_F32: fn = pool_kernel<ST_F32>(variant, sweep); break;
-    case ST_F32X: fn = pool_kernel<ST_F32X>(variant, sweep); break;
-    default: fn = pool_kernel<ST_F16>(variant, sweep); break;
+    case ST_F64: fn = pool_kernel<ST_F64>(variant, sweep, one); break;
+    case ST_F32: fn = pool_kernel<ST_F32>(variant, sweep, one); break;
+    case ST_F32X: fn = pool_kernel<ST_F32X>(variant, sweep, one); break;
+    default: fn = pool_kernel<ST_F16>(variant, sweep, one); break;
     }
     hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, stream, boxes, tstart, meta, k);
     return hipGetLastError();

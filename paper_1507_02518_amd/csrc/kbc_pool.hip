@@ -135,6 +135,7 @@ struct Slot {
 
 struct LaunchCfg {
     int block, grid, sub;   // threads per block, blocks (0: one per tile), sub-tiles per tile
+    bool one = false;       // a block for every tile and sub = 1: the single-tile kernel
 };
 
 // Launch groups: target footprint (populations of the group's boxes, a
@@ -177,8 +178,9 @@ struct kbc_pool {
     hipEvent_t mirror_ev[2] = {nullptr, nullptr};
     bool mirror_used[2] = {false, false};
     int mirror = 0;
-    // graphs keyed by (steps, block, grid, groups at parity 0, at parity 1)
-    using GraphKey = std::tuple<int64_t, int, int, int, int>;
+    // graphs keyed by (steps, block, grid, single-tile kernel, groups at
+    // parity 0, at parity 1)
+    using GraphKey = std::tuple<int64_t, int, int, bool, int, int>;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<GraphKey> graph_order;
     LaunchCfg cfg{256, 0, 1};          // the configuration of the latest batch
@@ -317,8 +319,9 @@ void destroy_graphs(kbc_pool* p)
 // 1: each group takes its `steps` steps before the next group starts.
 int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, int n0, int n1, hipGraphExec_t* out)
 {
-    // the sub-tile count lives in the uploaded table, not in the graph
-    const auto key = std::make_tuple(steps, cfg.block, cfg.grid, n0, n1);
+    // the sub-tile count lives in the uploaded table, not in the graph; the
+    // graph depends on it only through the choice of the single-tile kernel
+    const auto key = std::make_tuple(steps, cfg.block, cfg.grid, cfg.one, n0, n1);
     auto it = p->graphs.find(key);
     if (it != p->graphs.end()) {
         *out = it->second;
@@ -339,7 +342,8 @@ int get_graph(kbc_pool* p, int64_t steps, LaunchCfg cfg, int n0, int n1, hipGrap
             // a box at parity q takes the even sweep at steps k with k + q even
             const int sweep = ((parity + k) & 1) ? SW_AA_ODD : SW_AA_EVEN;
             err = launch_pool_step(p->dtype, p->variant, sweep, p->d_boxes, p->d_tstart,
-                                   p->d_meta + grp, (int)k, cfg.block, cfg.grid, p->stream);
+                                   p->d_meta + grp, (int)k, cfg.block, cfg.grid, cfg.one,
+                                   p->stream);
         }
     }
     const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
@@ -714,6 +718,8 @@ static int pool_advance(kbc_pool_handle p, int64_t g, const int32_t* only, int32
     hipGraphExec_t exec = nullptr;
     LaunchCfg gcfg = cfg;
     gcfg.grid = launch_grid(cfg, max_tiles);
+    // one block per tile (the grid covers the largest group) and no sub-tiles
+    gcfg.one = cfg.grid == 0 && cfg.sub == 1;
     if (int r = get_graph(p, batch, gcfg, ngroups[0], ngroups[1], &exec)) return r;
     if (cand >= 0) PHIP(hipEventRecord(p->tev0, p->stream));
     PHIP(hipGraphLaunch(exec, p->stream));

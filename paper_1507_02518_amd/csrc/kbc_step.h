@@ -315,8 +315,12 @@ typedef __attribute__((address_space(1))) char gchar;
 // belongs to the last box whose first tile is not after it (binary search
 // over the compact array of first tiles).  Boxes are disjoint in memory and
 // each node is updated by exactly one thread, so a box evolves exactly as it
-// would alone.
-template <int S, int V, int SW>
+// would alone.  ONE: the launch has a block for every tile and sub = 1, so a
+// block takes exactly one run of nodes; without the two loops the kernel
+// keeps no loop state in scalar registers (the FP32-X odd sweep spilled 27
+// of them to vector lanes) and runs one large box as fast as the single-box
+// kernel.
+template <int S, int V, int SW, bool ONE = false>
 __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __restrict__ table,
                                                              const uint32_t* __restrict__ ttable,
                                                              const PoolMeta* __restrict__ meta,
@@ -327,9 +331,9 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
     const uint32_t n_tiles = meta->n_tiles;
     const uint32_t n_active = meta->n_active;
     const uint32_t block = meta->block;
-    const uint32_t sub = meta->sub;
-#pragma unroll 1
-    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const uint32_t sub = ONE ? 1u : meta->sub;
+    // one tile; false when its box has no step to take in this launch
+    auto run_tile = [&](uint32_t tile) {
         uint32_t lo = 0, hi = n_active;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
             else hi = mid;
         }
         const PoolBox& b = boxes[lo];
-        if (k >= b.steps) continue;
+        if (k >= b.steps) return;
         // FP16: the box's scale exponents, staged in LDS once per tile so the
         // node update reads them there rather than from the box table
         __shared__ int8_t s_exp[28];
@@ -354,8 +358,7 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
         // saying so lets the compiler use global (not flat) loads and stores
         gchar* const gbuf = (gchar*)b.buf;
         const uint32_t first = (tile - tstart[lo]) * sub * block;
-#pragma unroll 1
-        for (uint32_t r = 0; r < sub; ++r) {
+        auto run = [&](uint32_t r) {
             const uint32_t n = first + r * block + threadIdx.x;
             if (n < g.nnodes) {
                 // loads and stores see the buffer through two global pointers,
@@ -367,7 +370,19 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
                 asm volatile("" : "+s"(dbuf));
                 node_update<S, V, SW>((void*)sbuf, (void*)dbuf, g, c, s_exp, n);
             }
+        };
+        if constexpr (ONE) {
+            run(0);
+        } else {
+#pragma unroll 1
+            for (uint32_t r = 0; r < sub; ++r) run(r);
         }
+    };
+    if constexpr (ONE) {
+        if (blockIdx.x < n_tiles) run_tile(blockIdx.x);
+    } else {
+#pragma unroll 1
+        for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
     }
 }
 

@@ -35,8 +35,9 @@ StepFn step_of_sweep(int sw, bool c64)
 }
 
 template <int V>
-PoolFn pool_of_sweep(int sw)
+PoolFn pool_of_sweep(int sw, bool one)
 {
+    if (one) return sw == SW_AA_EVEN ? k_pool_step<kS, V, SW_AA_EVEN, true> : k_pool_step<kS, V, SW_AA_ODD, true>;
     return sw == SW_AA_EVEN ? k_pool_step<kS, V, SW_AA_EVEN> : k_pool_step<kS, V, SW_AA_ODD>;
 }
 
@@ -80,22 +81,22 @@ template GammaFn gamma_kernel<kS, kGX>(int);
 #if !KBC_INST_EXACT
 // the pool runs the estimate gamma* only
 template <int S>
-PoolFn pool_kernel(int v, int sw)
+PoolFn pool_kernel(int v, int sw, bool one)
 {
     static_assert(S == kS, "instantiated for one storage form only");
     switch (v) {
-    case V_D: return pool_of_sweep<V_D>(sw);
-    case V_DT: return pool_of_sweep<V_DT>(sw);
-    case V_DQ: return pool_of_sweep<V_DQ>(sw);
-    case V_CD: return pool_of_sweep<V_CD>(sw);
-    case V_CDT: return pool_of_sweep<V_CDT>(sw);
-    case V_CDQ: return pool_of_sweep<V_CDQ>(sw);
-    case V_CDTQ: return pool_of_sweep<V_CDTQ>(sw);
-    default: return pool_of_sweep<V_DTQ>(sw);
+    case V_D: return pool_of_sweep<V_D>(sw, one);
+    case V_DT: return pool_of_sweep<V_DT>(sw, one);
+    case V_DQ: return pool_of_sweep<V_DQ>(sw, one);
+    case V_CD: return pool_of_sweep<V_CD>(sw, one);
+    case V_CDT: return pool_of_sweep<V_CDT>(sw, one);
+    case V_CDQ: return pool_of_sweep<V_CDQ>(sw, one);
+    case V_CDTQ: return pool_of_sweep<V_CDTQ>(sw, one);
+    default: return pool_of_sweep<V_DTQ>(sw, one);
     }
 }
 
-template PoolFn pool_kernel<kS>(int, int);
+template PoolFn pool_kernel<kS>(int, int, bool);
 #endif
 
 }  // namespace kbc

@@ -111,7 +111,8 @@ def test_pool_kernels_load_everything_before_storing(asm):
     between blocks); inside any block no population load may follow a
     population store."""
     names = re.findall(r"^(_ZN3kbc\S*k_pool_stepILi\dELi\dELi[12]E\S*):", asm, flags=re.M)
-    assert len(names) == 4 * 8 * 2
+    # 4 storage forms x 8 variants x 2 sweeps x (tile loop, single tile)
+    assert len(names) == 4 * 8 * 2 * 2
     for nm in names:
         storage = re.search(r"k_pool_stepILi(\d)E", nm).group(1)
         blocks = _blocks(asm, nm, storage)
@@ -144,7 +145,8 @@ def test_every_sweep_and_the_pool_collide_with_the_same_arithmetic(asm):
     floating-point instructions (same contractions into FMAs): per storage
     form and variant, the multiset of floating-point opcodes of the pull, AA
     even and AA odd step kernels (FP16 also the pull sweep on 64-node chunks)
-    and of the pool's two sweeps is the same."""
+    and of the pool's two sweeps (with and without the tile loop) is the
+    same."""
     names = re.findall(r"^(_ZN3kbc\S*(?:k_stepILi\dELi\dELi\dELb0|k_pool_stepILi\dELi\dELi\d)E\S*):",
                        asm, flags=re.M)
     groups = {}
@@ -153,8 +155,9 @@ def test_every_sweep_and_the_pool_collide_with_the_same_arithmetic(asm):
         groups.setdefault((m.group(2), m.group(3)), []).append((nm, _fp_ops(asm, nm)))
     assert len(groups) == 4 * 8
     for key, lst in groups.items():
-        # FP16 (storage 2) adds the pull sweep on 64-node chunks
-        assert len(lst) == (6 if key[0] == "2" else 5), (key, len(lst))
+        # pull, AA even, AA odd, the pool's two sweeps with and without the
+        # tile loop; FP16 (storage 2) adds the pull sweep on 64-node chunks
+        assert len(lst) == (8 if key[0] == "2" else 7), (key, len(lst))
         ref = lst[0][1]
         assert sum(ref.values()) > 300, key
         for nm, ops in lst[1:]:
