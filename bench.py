@@ -113,9 +113,10 @@ def valu_issue_ms(counts, storage, streaming, var, n):
     nodes), from the measured counts: the kernel's VALU issue bound."""
     gx = "true" if var == "exact" else "false"
     sweeps = (0,) if streaming == "PULL" else (1, 2)
-    # FP16 pull boxes in 64-node chunks run the kernel with that geometry
-    # compiled in
-    c64 = "true" if storage == "F16_DEV" and streaming == "PULL" and n % 64 == 0 and n > 64 else "false"
+    # FP16 and exact-stabilizer pull boxes in 64-node chunks run the kernel
+    # with that geometry compiled in
+    c64 = ("true" if streaming == "PULL" and n % 64 == 0 and n > 64
+           and (storage == "F16_DEV" or var == "exact") else "false")
     names = [f"k_step<{STORAGE_INDEX[storage]}, {VARIANT_INDEX[var]}, {sw}, {gx}, "
              f"{c64 if sw == 0 else 'false'}>" for sw in sweeps]
     if not all(nm in counts for nm in names):
