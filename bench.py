@@ -154,23 +154,42 @@ def time_form(kbc, torch, u_dev, dtype, streaming, steps, warmup, stream, varian
 
 
 def copy_ceiling(kbc, torch, stream):
-    """Achievable HBM bandwidth of a plain streaming copy (2 x 2 GiB)."""
+    """Achievable HBM bandwidth of a plain streaming copy between two 2 GiB
+    buffers, and of the same stream in place (each 16-byte word read and
+    written back to its own address, as an in-place AA sweep does), in GB/s
+    counting the bytes read plus the bytes written."""
     nbytes = 2 << 30
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    for _ in range(3):
-        kbc.kbc_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    reps = 20
-    e0.record(stream)
-    for _ in range(reps):
-        kbc.kbc_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = []
+    for dst in (b, a):
+        for _ in range(3):
+            kbc.kbc_hbm_copy(dst.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            kbc.kbc_hbm_copy(dst.data_ptr(), a.data_ptr(), nbytes, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out.append(2 * nbytes / (ms * 1e-3) / 1e9)
     del a, b
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out[0], out[1]
+
+
+def add_ceiling_fracs(forms, copy_gbs, inplace_gbs):
+    """Each form's algorithmic GB/s against the measured ceiling of its
+    streaming: the copy between two buffers for pull, the in-place stream
+    for AA."""
+    for name, r in forms.items():
+        if not isinstance(r, dict) or "algorithmic_GBs" not in r:
+            continue
+        if "_aa" in name:
+            r["frac_of_inplace_ceiling"] = round(r["algorithmic_GBs"] / inplace_gbs, 4)
+        else:
+            r["frac_of_copy_ceiling"] = round(r["algorithmic_GBs"] / copy_gbs, 4)
 
 
 def ensemble_and_serving(kbc, args):
@@ -511,8 +530,10 @@ def main():
 
     forms = run_forms(kbc, torch, u_dev, FORMS_256, forms_256, args.steps, args.warmup, stream,
                       N, NU)
-    log("[bench] copy ceiling")
-    copy_gbs = copy_ceiling(kbc, torch, stream)
+    log("[bench] copy ceiling (between two buffers and in place)")
+    copy_gbs, inplace_gbs = copy_ceiling(kbc, torch, stream)
+    log(f"[bench]   {copy_gbs:.0f} GB/s copy, {inplace_gbs:.0f} GB/s in place")
+    add_ceiling_fracs(forms, copy_gbs, inplace_gbs)
     del u_dev
     torch.cuda.empty_cache()
 
@@ -524,6 +545,7 @@ def main():
         table = [(nm, dt, "AA", None) for nm, dt in BIG_FORMS]
         big = run_forms(kbc, torch, ub, table, forms_512, args.big_steps, args.big_warmup, stream,
                         BIG_N, BIG_NU)
+        add_ceiling_fracs(big, copy_gbs, inplace_gbs)
         del ub
         torch.cuda.empty_cache()
 
@@ -542,6 +564,7 @@ def main():
         "nodes_per_launch": N ** 3,
         "copy_ceiling_GBs": round(copy_gbs, 1),
         "frac_of_copy_ceiling": round(head["algorithmic_GBs"] / copy_gbs, 4),
+        "inplace_ceiling_GBs": round(inplace_gbs, 1),
     }
     cpu = None
     if not args.no_cpu:

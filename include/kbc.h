@@ -327,7 +327,11 @@ int kbc_pool_set_launch(kbc_pool_handle p, int32_t block, int32_t grid, int32_t 
  * 16) from device src to device dst with a plain streaming kernel on the
  * given hipStream_t (NULL = default stream), without synchronising.  Its
  * duration and HBM counters give the achievable copy bandwidth and the
- * scale of the rocprof FETCH_SIZE / WRITE_SIZE counters against known bytes. */
+ * scale of the rocprof FETCH_SIZE / WRITE_SIZE counters against known bytes.
+ * With dst == src every 16-byte word is read and written back unchanged at
+ * its own address (the traffic of an in-place sweep, which streams slower
+ * than a copy between two buffers); other overlapping ranges are rejected
+ * (KBC_EINVAL). */
 int kbc_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Message of the last failed call on this thread ("" if none).  Valid until

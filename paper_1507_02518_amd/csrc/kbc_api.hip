@@ -848,6 +848,12 @@ int kbc_hbm_copy(void* dst, const void* src, size_t bytes, void* stream)
 {
     if (!dst || !src) return fail(KBC_EINVAL, "dst or src is NULL");
     if (bytes % 16) return fail(KBC_EINVAL, "bytes must be a multiple of 16");
+    if (dst == src) {
+        KBC_HIP(launch_rewrite16(dst, bytes / 16, (hipStream_t)stream));
+        return KBC_OK;
+    }
+    const uintptr_t d = (uintptr_t)dst, s = (uintptr_t)src;
+    if (d < s + bytes && s < d + bytes) return fail(KBC_EINVAL, "dst and src overlap");
     KBC_HIP(launch_copy16(dst, src, bytes / 16, (hipStream_t)stream));
     return KBC_OK;
 }

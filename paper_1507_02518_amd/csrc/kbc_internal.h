@@ -108,6 +108,7 @@ hipError_t launch_moments(int storage, int layout, const void* buf, const Geom& 
 
 // Plain streaming copy of n16 16-byte words.
 hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t stream);
+hipError_t launch_rewrite16(void* p, size_t n16, hipStream_t stream);
 
 // Deterministic FP64 reductions over a velocity field u [3][N].
 //   kind 0: out[0..2] = sum_x u_a(x)

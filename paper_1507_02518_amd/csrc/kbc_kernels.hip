@@ -532,6 +532,21 @@ __global__ void __launch_bounds__(kBlock) k_copy16(u32x4* __restrict__ dst,
         __builtin_nontemporal_store(src[k], &dst[k]);
 }
 
+// The same stream in place: every 16-byte word is read and written back to
+// its own address, the access pattern of an in-place sweep.  `mask` is zero
+// at run time (the data stays as it was); XOR-ing it into all four lanes
+// keeps the compiler from dropping (or narrowing) the store of a value just
+// loaded from the same address.
+__global__ void __launch_bounds__(kBlock) k_rewrite16(u32x4* p, size_t n16, uint32_t mask)
+{
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < n16; k += stride) {
+        u32x4 v = p[k];
+        v ^= mask;
+        __builtin_nontemporal_store(v, &p[k]);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -685,6 +700,16 @@ hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t str
     const unsigned blocks = (unsigned)std::min<size_t>(want, 1u << 21);
     hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<u32x4*>(dst),
                        static_cast<const u32x4*>(src), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_rewrite16(void* p, size_t n16, hipStream_t stream)
+{
+    if (n16 == 0) return hipSuccess;
+    const size_t want = (n16 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)std::min<size_t>(want, 1u << 21);
+    hipLaunchKernelGGL(k_rewrite16, dim3(blocks), dim3(kBlock), 0, stream, static_cast<u32x4*>(p),
+                       n16, 0u);
     return hipGetLastError();
 }
 

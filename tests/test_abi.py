@@ -117,6 +117,20 @@ def test_null_handles_are_rejected():
     assert b"null handle" in lib.kbc_last_error()
 
 
+def test_hbm_copy_rejects_bad_arguments():
+    """Argument errors of the copy utility come back before any launch (the
+    addresses below are never dereferenced)."""
+    lib = kbc.load()
+    p, q = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    assert lib.kbc_hbm_copy(None, q, 64, None) == kbc.KBC_EINVAL
+    assert lib.kbc_hbm_copy(p, q, 24, None) == kbc.KBC_EINVAL
+    assert b"multiple of 16" in lib.kbc_last_error()
+    # overlapping but distinct ranges, in both orders
+    assert lib.kbc_hbm_copy(ctypes.c_void_p(0x100010), p, 64, None) == kbc.KBC_EINVAL
+    assert lib.kbc_hbm_copy(p, ctypes.c_void_p(0x100030), 64, None) == kbc.KBC_EINVAL
+    assert b"overlap" in lib.kbc_last_error()
+
+
 def test_fast_division_host_check():
     clang = "/opt/rocm/llvm/bin/clang++"
     if not os.path.exists(clang):
