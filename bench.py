@@ -489,7 +489,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-policies", default="aged,loop",
                     help="comma list of aged, srpt, loop")
-    ap.add_argument("--serve-reps", type=int, default=1)
+    ap.add_argument("--serve-reps", type=int, default=2,
+                    help="repetitions per policy, interleaved (the line gives their spread)")
     ap.add_argument("--precision", action="store_true",
                     help="run the storage-precision study (128^3 and 512^3) instead")
     ap.add_argument("--precision-steps-512", type=int, default=2000)
