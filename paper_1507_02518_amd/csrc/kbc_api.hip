@@ -128,16 +128,35 @@ void* state_buf(const kbc_box* h)
     return h->streaming == KBC_PULL ? h->buf[h->cur] : h->buf[0];
 }
 
-int ensure_diag(kbc_handle h, bool need_pop)
+// The small device buffers of a box (a few KB): reduction partials and
+// sums, the non-finite flag, the FP16 maxima.
+int ensure_small(kbc_handle h)
 {
-    const size_t N = h->g.nnodes;
-    if (!h->d_u) KBC_HIP(hipMalloc(&h->d_u, 3 * N * sizeof(double)));
-    if (!h->d_rho) KBC_HIP(hipMalloc(&h->d_rho, N * sizeof(double)));
     if (!h->d_partial) KBC_HIP(hipMalloc(&h->d_partial, 8 * (size_t)reduce_partials() * sizeof(double)));
     if (!h->d_sum) KBC_HIP(hipMalloc(&h->d_sum, 32 * sizeof(double)));
     if (!h->d_flag) KBC_HIP(hipMalloc(&h->d_flag, sizeof(int)));
     if (!h->d_max) KBC_HIP(hipMalloc(&h->d_max, 27 * sizeof(unsigned)));
-    if (need_pop && !h->d_pop) KBC_HIP(hipMalloc(&h->d_pop, 27 * N * sizeof(double)));
+    return KBC_OK;
+}
+
+// The large buffers are allocated on first use, so that a box that is only
+// initialised from device memory and stepped holds its populations and the
+// small buffers alone: the velocity field the diagnostics reduce over (24 B
+// per node), the density when asked for (8 B per node), the FP64 population
+// copy of get / set populations (216 B per node).
+int ensure_diag(kbc_handle h, bool need_rho)
+{
+    if (int r = ensure_small(h)) return r;
+    const size_t N = h->g.nnodes;
+    if (!h->d_u) KBC_HIP(hipMalloc(&h->d_u, 3 * N * sizeof(double)));
+    if (need_rho && !h->d_rho) KBC_HIP(hipMalloc(&h->d_rho, N * sizeof(double)));
+    return KBC_OK;
+}
+
+int ensure_pop(kbc_handle h)
+{
+    if (int r = ensure_small(h)) return r;
+    if (!h->d_pop) KBC_HIP(hipMalloc(&h->d_pop, 27 * (size_t)h->g.nnodes * sizeof(double)));
     return KBC_OK;
 }
 
@@ -164,7 +183,7 @@ void choose_scales(kbc_handle h, const unsigned* max_bits)
 // when a value is not finite.
 int compute_moments(kbc_handle h, bool want_rho)
 {
-    int r = ensure_diag(h, false);
+    int r = ensure_diag(h, want_rho);
     if (r) return r;
     KBC_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), h->stream));
     KBC_HIP(launch_moments(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale,
@@ -453,7 +472,7 @@ int kbc_destroy(kbc_handle h)
 
 static int init_from_device(kbc_handle h, const double* du, const double* drho)
 {
-    int r = ensure_diag(h, false);
+    int r = ensure_small(h);
     if (r) return r;
     KBC_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), h->stream));
     KBC_HIP(launch_check_init(h->g, du, drho, h->d_flag, h->stream));
@@ -485,7 +504,7 @@ int kbc_init_velocity(kbc_handle h, const double* u, const double* rho)
     if (int r = check_handle(h)) return r;
     if (!u) return fail(KBC_EINVAL, "u is NULL");
     if (int r = set_device(h)) return r;
-    int r = ensure_diag(h, false);
+    int r = ensure_diag(h, rho != nullptr);
     if (r) return r;
     const size_t N = h->g.nnodes;
     KBC_HIP(hipMemcpyAsync(h->d_u, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -690,7 +709,7 @@ int kbc_gamma_statistics(kbc_handle h, double out[4])
     if (!out) return fail(KBC_EINVAL, "out is NULL");
     if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
     if (int r = set_device(h)) return r;
-    if (int r = ensure_diag(h, false)) return r;
+    if (int r = ensure_small(h)) return r;
     KBC_HIP(launch_gamma_stats(h->dtype, h->variant, h->exact_gamma, layout_now(h), state_buf(h),
                                h->g, h->coll, h->inv_scale, h->d_partial, h->d_sum + 16,
                                h->stream));
@@ -744,7 +763,7 @@ int kbc_get_populations(kbc_handle h, double* f)
     if (!f) return fail(KBC_EINVAL, "f is NULL");
     if (!h->initialised) return fail(KBC_ESTATE, "box has no state");
     if (int r = set_device(h)) return r;
-    if (int r = ensure_diag(h, true)) return r;
+    if (int r = ensure_pop(h)) return r;
     KBC_HIP(launch_gather_pop(h->dtype, layout_now(h), state_buf(h), h->g, h->inv_scale, h->d_pop,
                               h->stream));
     KBC_HIP(hipStreamSynchronize(h->stream));
@@ -792,7 +811,7 @@ int kbc_set_populations(kbc_handle h, const double* f, int64_t t)
     if (!f) return fail(KBC_EINVAL, "f is NULL");
     if (t < 0) return fail(KBC_EINVAL, "t must be >= 0");
     if (int r = set_device(h)) return r;
-    if (int r = ensure_diag(h, true)) return r;
+    if (int r = ensure_pop(h)) return r;
     KBC_HIP(hipStreamSynchronize(h->stream));
     KBC_HIP(hipMemcpy(h->d_pop, f, 27ull * h->g.nnodes * sizeof(double), hipMemcpyHostToDevice));
     if (h->dtype == KBC_F16_DEV && !h->scales_set) {

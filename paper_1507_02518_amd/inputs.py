@@ -13,6 +13,8 @@ the GPU path and its CPU oracle start from.
 * ``kida``: the Kida vortex of section V.
 * ``shear_wave``: u_x = U sin(2 pi y / N_y), the viscosity probe.
 * ``smooth_random``: a few random Fourier modes on any (ragged) box.
+* ``smooth_random_device``: the same kind of field built in device memory
+  (torch), for boxes too large to build on the host.
 """
 from __future__ import annotations
 
@@ -130,6 +132,33 @@ def smooth_random(shape, amplitude: float = 0.03, modes: int = 4, seed: int = 0)
             ph = rng.uniform(0, 2 * np.pi)
             amp = rng.uniform(-1, 1) * amplitude / modes
             u[a] += amp * np.sin(kx * x + ky * y + kz * z + ph)
+    return u
+
+
+def smooth_random_device(shape, amplitude: float = 0.1, modes: int = 4, seed: int = 0,
+                         device: str = "cuda"):
+    """Sum of `modes` plane waves per component, built as a float64 torch
+    tensor [3][nz][ny][nx] on `device`: every wave has wave numbers 1-3 with
+    a random sign along each axis (so no axis is uniform) and a random phase,
+    amplitude / modes each, so |u_a| <= amplitude."""
+    import torch
+
+    nx, ny, nz = _shape3(shape)
+    rng = np.random.default_rng(seed)
+
+    def coord(n):
+        return torch.arange(n, dtype=torch.float64, device=device) * (2.0 * np.pi / n)
+
+    x, y, z = coord(nx), coord(ny), coord(nz)
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device=device)
+    for a in range(3):
+        for _ in range(modes):
+            k = rng.integers(1, 4, size=3) * rng.choice([-1, 1], size=3)
+            ph = float(rng.uniform(0, 2 * np.pi))
+            arg = ((float(k[2]) * z)[:, None, None] + (float(k[1]) * y)[None, :, None]
+                   + (float(k[0]) * x + ph)[None, None, :])
+            u[a].add_(arg.sin_(), alpha=amplitude / modes)
+            del arg
     return u
 
 

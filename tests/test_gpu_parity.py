@@ -524,6 +524,70 @@ def test_full_size_512_aa_sampled_against_oracle(orc, hit512, dtype, tol):
     assert err <= tol
 
 
+# ---------------------------------------------------- maximum sizes ----
+
+def _lightcone_from_device(orc, u_dev, nodes, steps, nu, shape):
+    """As _lightcone_reference, for a start held in device memory: each
+    node's (2 steps + 1)^3 block is gathered from the device tensor, so the
+    oracle starts from exactly the values the GPU run starts from."""
+    import torch
+
+    nx, ny, nz = shape
+    r = steps
+    out = []
+    for n in nodes:
+        x, y, z = int(n % nx), int((n // nx) % ny), int(n // (nx * ny))
+        ix, iy, iz = (torch.arange(c - r, c + r + 1, device=u_dev.device) % m
+                      for c, m in ((x, nx), (y, ny), (z, nz)))
+        ub = u_dev[:, iz[:, None, None], iy[None, :, None], ix[None, None, :]].cpu().numpy()
+        out.append(_oracle_run(orc, np.ascontiguousarray(ub), nu, steps)[:, r, r, r])
+    return np.array(out)
+
+
+# The largest boxes kbc_create accepts.  FP64 with 2^29 nodes: a direction
+# plane of exactly 4 GiB, so the last node's byte offset in its plane is
+# 2^32 - 8, the top of the step kernels' 32-bit offsets.  FP16 just below
+# 2^31 nodes, the node-index limit (in place), and FP16 pull on 2^30 nodes
+# (planes of 2 GiB, spaced by the gap).  The start has |u_a| <= 0.1
+# (deviations up to about 0.025); the bounds are those of the 512^3 run.
+MAX_CASES = [((1024, 1024, 512), kbc.F64, kbc.AA, 3, 1e-14),
+             ((2048, 1024, 1023), kbc.F16_DEV, kbc.AA, 3, 1e-4),
+             ((1024, 1024, 1024), kbc.F16_DEV, kbc.PULL, 2, 1e-4)]
+
+
+@pytest.mark.parametrize("shape,dtype,streaming,steps,tol", MAX_CASES)
+def test_maximum_size_boxes_sampled_against_oracle(orc, shape, dtype, streaming, steps, tol):
+    """A smooth multi-mode start built on the GPU, a few steps (AA: even,
+    odd, even), then 32 nodes (the first and last of a plane, the ends of
+    the first and last row and slab, the middle, random ones) against the
+    oracle's light-cone evolution of the same start."""
+    import torch
+
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    nu = 2.5e-4
+    say(f"max size {shape} dtype={dtype} streaming={streaming}: start on the GPU")
+    torch.cuda.empty_cache()
+    u = inputs.smooth_random_device(shape, amplitude=0.1, modes=4, seed=nz)
+    torch.cuda.synchronize()
+    fixed = [0, N - 1, nx - 1, nx * (ny - 1), nx * ny - 1, nx * ny * (nz - 1),
+             nx * ny * (nz - 1) + nx - 1, N - nx, N // 2 + nx // 2]
+    rng = np.random.default_rng(nz)
+    nodes = np.concatenate([fixed, rng.integers(0, N, size=32 - len(fixed))])
+    ref = _lightcone_from_device(orc, u, nodes, steps, nu, shape)
+    with _box(shape, nu, dtype, streaming=streaming) as b:
+        kbc.kbc_init_velocity_device(b.h, u.data_ptr())
+        del u
+        torch.cuda.empty_cache()
+        b.step(steps)
+        assert b.t == steps
+        got = b.sample(nodes)
+    err = np.abs(got - ref).max()
+    say(f"max size {shape} dtype={dtype} streaming={streaming}: sampled max|df| {err:.3e} "
+        f"(bound {tol:.0e})")
+    assert err <= tol
+
+
 # ------------------------------------------------ deviation storage ----
 
 # Bounds are about 2-5x the measured errors (FP32 collision on FP32 storage:
