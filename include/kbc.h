@@ -114,7 +114,15 @@ void kbc_options_default(kbc_options* opt);
  * kbc_init_velocity or kbc_set_populations.  On success *out owns the box.
  * The device layout of the populations is internal (x-blocked for pull boxes
  * whose lattice spans less than 4 GiB, one plane per direction otherwise)
- * and never crosses this interface. */
+ * and never crosses this interface.  Some calls add device buffers on their
+ * first use, kept until kbc_destroy: the velocity field the diagnostics
+ * reduce over (24 B per node; 8 B more per node for a density that is read
+ * or passed in) for kbc_init_velocity from host memory, kbc_moments,
+ * kbc_energy, kbc_energy_series, kbc_enstrophy, kbc_statistics and
+ * kbc_correlation; an FP64 copy of the populations (216 B per node) for
+ * kbc_get_populations and kbc_set_populations.  kbc_init_velocity_device,
+ * kbc_step, kbc_sample_populations, kbc_gamma_statistics and the
+ * no-allocation energy series add none of them. */
 int kbc_create(const int64_t shape[3], double nu, int32_t dtype,
                const kbc_options* opt, kbc_handle* out);
 
