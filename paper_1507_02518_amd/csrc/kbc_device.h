@@ -110,6 +110,9 @@ struct StepParams {
     Coll c;
     // FP16 storage: stored = (f - W) * 2^scale_exp[i]; zero for the other forms
     int8_t scale_exp[28];
+    // nonzero: each XCD takes one contiguous eighth of the workgroups (the
+    // host sets it for AA sweeps over large slabs, see k_step)
+    uint32_t xcd_blocks;
 };
 
 __host__ __device__ __forceinline__ float ldexp_(float x, int e)

@@ -35,9 +35,6 @@ constexpr int kBlock = 256;
 #ifndef KBC_AA_ALIGNED
 #define KBC_AA_ALIGNED 1
 #endif
-#ifndef KBC_XCD_REMAP
-#define KBC_XCD_REMAP 0
-#endif
 constexpr int kStepBlock = KBC_STEP_BLOCK;
 
 template <typename T>
@@ -259,18 +256,21 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 }
 
 // Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals
-// workgroups to the eight XCDs in turn).  With KBC_XCD_REMAP (a build
-// option, off by default) each XCD takes one contiguous eighth of the box
-// instead: XCD j's k-th workgroup gets range start(j) + k, so that
-// workgroups sharing cache lines (the two ends of a row split between
-// workgroups, read shifted by one node in x) meet in one L2.  Measured on
-// MI355X: FP64 AA at 512^3 7% faster, but FP64 AA at 256^3 10% and the pull
-// sweep 1.4% slower, FP32/FP16 AA at 512^3 1-2% slower (eight separate
-// fronts through HBM instead of one).  The exact stabilizer (ALU-bound,
-// one-wave workgroups) keeps the plain order in any case.
-__device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, bool exact)
+// workgroups to the eight XCDs in turn), so in the plain order the eight
+// XCDs advance through the box side by side, one front.  With `remap` each
+// XCD takes one contiguous eighth of the box instead (XCD j's k-th
+// workgroup gets block start(j) + k): eight fronts, each reading the z - 1
+// and z + 1 slabs of its own nodes shortly after its own L2 and the
+// last-level cache saw them.  The host asks for it where the three slabs an
+// AA sweep reads at once, over all 27 planes, exceed half of the 256 MB
+// last-level cache (FP64 at 512^3: 170 MB, 7-9% faster per sweep pair); on
+// smaller slabs the single front measured faster (FP64 AA at 256^3 9%,
+// FP32 and FP16 AA at 512^3 0-2%).  The pull sweep (FP64 at 512^3 the same
+// either way) and the exact stabilizer (ALU-bound, one-wave workgroups)
+// keep the plain order.
+__device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, bool remap)
 {
-    if (!KBC_XCD_REMAP || exact) return b;
+    if (!remap) return b;
     const uint32_t j = b & 7u, k = b >> 3, q = grid >> 3, r = grid & 7u;
     return j * q + (j < r ? j : r) + k;
 }
@@ -290,7 +290,8 @@ __attribute__((amdgpu_waves_per_eu(GX ? KBC_GX_WAVES_PER_EU : 1, 8)))
 #endif
 k_step(StepParams p)
 {
-    const uint32_t n0 = step_block(blockIdx.x, gridDim.x, GX) * blockDim.x;
+    const uint32_t n0 =
+        step_block(blockIdx.x, gridDim.x, SW != SW_PULL && !GX && p.xcd_blocks) * blockDim.x;
     const uint32_t n = n0 + threadIdx.x;
     // aligned stores where the exchange costs no occupancy: FP64 (2 waves
     // per SIMD either way) and FP32 with the FP64-formed non-equilibrium (3);
