@@ -86,7 +86,7 @@ struct kbc_box {
     int8_t scale_exp[28];   // the same scales as powers of two, for the step kernels
     bool scales_set;
     bool initialised;
-    bool xcd_blocks;   // AA sweeps in XCD-contiguous workgroup order (k_step)
+    bool xcd_eighths;  // AA sweeps with one eighth of the workgroups per XCD (step_block)
     // diagnostics scratch (allocated on first use)
     double* d_u;
     double* d_rho;
@@ -229,7 +229,7 @@ StepParams step_params(const kbc_box* h)
     p.c = h->coll;
     static_assert(sizeof(p.scale_exp) == sizeof(h->scale_exp), "exponent layout");
     std::memcpy(p.scale_exp, h->scale_exp, sizeof(p.scale_exp));
-    p.xcd_blocks = h->xcd_blocks ? 1u : 0u;
+    p.xcd_order = h->xcd_eighths ? ORDER_EIGHTHS : ORDER_PAIRS;
     return p;
 }
 
@@ -408,8 +408,9 @@ int kbc_create(const int64_t shape[3], double nu, int32_t dtype, const kbc_optio
     h->variant = opt.variant;
     h->streaming = opt.streaming;
     // AA sweeps whose three z-slabs over the 27 planes exceed half of the
-    // last-level cache run in XCD-contiguous workgroup order (k_step)
-    h->xcd_blocks = opt.streaming == KBC_AA &&
+    // last-level cache give each XCD one contiguous eighth of the
+    // workgroups, the others consecutive pairs (step_block)
+    h->xcd_eighths = opt.streaming == KBC_AA &&
                     3.0 * 27.0 * (double)h->g.slab * (double)elem_bytes(dtype) > 128.0 * 1048576.0;
     h->nu = nu;
     // nu = c_s^2 (1/(2 beta) - 1/2), c_s^2 = 1/3

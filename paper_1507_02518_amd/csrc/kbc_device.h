@@ -103,6 +103,9 @@ struct Coll {
     int32_t pad_;
 };
 
+// Orders of a launch's workgroups over the eight XCDs (see step_block).
+enum XcdOrder : uint32_t { ORDER_PLAIN = 0, ORDER_PAIRS = 1, ORDER_EIGHTHS = 2 };
+
 struct StepParams {
     const void* src;
     void* dst;
@@ -110,9 +113,9 @@ struct StepParams {
     Coll c;
     // FP16 storage: stored = (f - W) * 2^scale_exp[i]; zero for the other forms
     int8_t scale_exp[28];
-    // nonzero: each XCD takes one contiguous eighth of the workgroups (the
-    // host sets it for AA sweeps over large slabs, see k_step)
-    uint32_t xcd_blocks;
+    // order of the workgroups over the XCDs in the AA sweeps (step_block):
+    // ORDER_PAIRS or ORDER_EIGHTHS, set by the host per box
+    uint32_t xcd_order;
 };
 
 __host__ __device__ __forceinline__ float ldexp_(float x, int e)

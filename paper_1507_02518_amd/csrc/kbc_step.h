@@ -256,23 +256,39 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 }
 
 // Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals
-// workgroups to the eight XCDs in turn), so in the plain order the eight
-// XCDs advance through the box side by side, one front.  With `remap` each
-// XCD takes one contiguous eighth of the box instead (XCD j's k-th
-// workgroup gets block start(j) + k): eight fronts, each reading the z - 1
-// and z + 1 slabs of its own nodes shortly after its own L2 and the
-// last-level cache saw them.  The host asks for it where the three slabs an
-// AA sweep reads at once, over all 27 planes, exceed half of the 256 MB
-// last-level cache (FP64 at 512^3: 170 MB, 7-9% faster per sweep pair); on
-// smaller slabs the single front measured faster (FP64 AA at 256^3 9%,
-// FP32 and FP16 AA at 512^3 0-2%).  The pull sweep (FP64 at 512^3 the same
-// either way) and the exact stabilizer (ALU-bound, one-wave workgroups)
-// keep the plain order.
-__device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, bool remap)
+// workgroups to the eight XCDs in turn).  ORDER_PLAIN keeps that: the XCDs
+// advance through the box side by side, one front, and consecutive
+// workgroups sit in different L2 caches.  The AA sweeps take one of two
+// other orders, chosen by the host per box:
+//   ORDER_PAIRS: XCD x's k-th workgroup takes block 2 (8 (k / 2) + x) +
+//   k % 2, still one front, but each XCD takes two consecutive blocks, so
+//   the two halves of a 512-node row (read shifted by one node in x by the
+//   odd sweep) meet in one L2.  FP16 AA at 512^3 2.7-5.4% and FP32 AA 1-3.6%
+//   faster than the plain order; the same at 256^3 (one workgroup per row).
+//   ORDER_EIGHTHS: each XCD takes one contiguous eighth of the blocks (XCD
+//   j's k-th workgroup gets block start(j) + k), eight fronts, each reading
+//   the z - 1 and z + 1 slabs of its own nodes.  Taken where the three
+//   slabs an AA sweep reads at once, over all 27 planes, exceed half of the
+//   256 MB last-level cache (FP64 at 512^3: 170 MB, 7-9% faster per sweep
+//   pair); on smaller slabs one front measured faster (FP64 AA at 256^3 9%,
+//   FP32 and FP16 AA at 512^3 0-2%).
+// The pull sweep (FP64 at 512^3 the same in either order) and the exact
+// stabilizer (ALU-bound, one-wave workgroups) keep the plain order.  Blocks
+// past the last whole group of 16 (pairs) or at the tail (eighths) keep
+// their index in the pairs order and are spread in the eighths order.
+__device__ __forceinline__ uint32_t step_block(uint32_t b, uint32_t grid, uint32_t order)
 {
-    if (!remap) return b;
-    const uint32_t j = b & 7u, k = b >> 3, q = grid >> 3, r = grid & 7u;
-    return j * q + (j < r ? j : r) + k;
+    if (order == ORDER_PAIRS) {
+        const uint32_t full = grid & ~15u;
+        if (b >= full) return b;
+        const uint32_t x = b & 7u, k = b >> 3;
+        return ((k >> 1) * 8u + x) * 2u + (k & 1u);
+    }
+    if (order == ORDER_EIGHTHS) {
+        const uint32_t j = b & 7u, k = b >> 3, q = grid >> 3, r = grid & 7u;
+        return j * q + (j < r ? j : r) + k;
+    }
+    return b;
 }
 
 // Fused step of one box: one thread per node, workgroups of up to
@@ -291,7 +307,8 @@ __attribute__((amdgpu_waves_per_eu(GX ? KBC_GX_WAVES_PER_EU : 1, 8)))
 k_step(StepParams p)
 {
     const uint32_t n0 =
-        step_block(blockIdx.x, gridDim.x, SW != SW_PULL && !GX && p.xcd_blocks) * blockDim.x;
+        step_block(blockIdx.x, gridDim.x, SW != SW_PULL && !GX ? p.xcd_order : ORDER_PLAIN) *
+        blockDim.x;
     const uint32_t n = n0 + threadIdx.x;
     // aligned stores where the exchange costs no occupancy: FP64 (2 waves
     // per SIMD either way) and FP32 with the FP64-formed non-equilibrium (3);
