@@ -264,7 +264,9 @@ __device__ __forceinline__ void node_update(const void* srcv, void* dstv, const 
 //   k % 2, still one front, but each XCD takes two consecutive blocks, so
 //   the two halves of a 512-node row (read shifted by one node in x by the
 //   odd sweep) meet in one L2.  FP16 AA at 512^3 2.7-5.4% and FP32 AA 1-3.6%
-//   faster than the plain order; the same at 256^3 (one workgroup per row).
+//   faster than the plain order.  Taken only where a row is longer than a
+//   workgroup: on shorter rows nothing is split, and boxes of 128^3 (in the
+//   last-level cache) ran 15-21% slower in pairs (FP32-X, FP16).
 //   ORDER_EIGHTHS: each XCD takes one contiguous eighth of the blocks (XCD
 //   j's k-th workgroup gets block start(j) + k), eight fronts, each reading
 //   the z - 1 and z + 1 slabs of its own nodes.  Taken where the three
@@ -306,9 +308,11 @@ __attribute__((amdgpu_waves_per_eu(GX ? KBC_GX_WAVES_PER_EU : 1, 8)))
 #endif
 k_step(StepParams p)
 {
-    const uint32_t n0 =
-        step_block(blockIdx.x, gridDim.x, SW != SW_PULL && !GX ? p.xcd_order : ORDER_PLAIN) *
-        blockDim.x;
+    // pairs only where a row is longer than a workgroup: the halves of a
+    // split row are what that order keeps in one L2
+    uint32_t order = SW != SW_PULL && !GX ? p.xcd_order : ORDER_PLAIN;
+    if (order == ORDER_PAIRS && p.g.nx <= blockDim.x) order = ORDER_PLAIN;
+    const uint32_t n0 = step_block(blockIdx.x, gridDim.x, order) * blockDim.x;
     const uint32_t n = n0 + threadIdx.x;
     // aligned stores where the exchange costs no occupancy: FP64 (2 waves
     // per SIMD either way) and FP32 with the FP64-formed non-equilibrium (3);
@@ -397,11 +401,7 @@ __global__ void __launch_bounds__(kPoolMaxBlock) k_pool_step(const PoolBox* __re
         }
     };
     if constexpr (ONE) {
-        // consecutive tiles in pairs on one XCD (step_block), so that more of
-        // a small box's neighbour rows and slabs stay in one L2: the 64-box
-        // ensemble ran 1.3-1.4% faster than with tile b on XCD b mod 8
-        const uint32_t tile = step_block(blockIdx.x, gridDim.x, ORDER_PAIRS);
-        if (tile < n_tiles) run_tile(tile);
+        if (blockIdx.x < n_tiles) run_tile(blockIdx.x);
     } else {
 #pragma unroll 1
         for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
