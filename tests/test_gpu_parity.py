@@ -165,6 +165,38 @@ def test_layouts_in_every_storage_form(orc, shape, dtype, tol, streaming):
     assert err <= tol
 
 
+# The AA sweeps hand workgroups to the eight XCDs in one of three orders
+# (step_block), with grids that need not divide evenly: (300, 5, 3) has rows
+# longer than a workgroup (the pairs order) and 18 workgroups, two past the
+# last whole group of 16; (520, 400, 3) in FP64 has z-slabs large enough for
+# the eighths order (3 x 27 x 520 x 400 x 8 B = 135 MB) and 2438 workgroups,
+# six more than a multiple of 8; in FP32-X the same box takes the pairs order
+# with a tail of six.  A missed or doubled node gives errors of order 1e-2;
+# the bounds are those of the layout test above (the larger box reaches
+# larger velocities, so its FP32-X bound is 1e-7).
+_ORDER_ORACLE = {}
+ORDER_CASES = [((300, 5, 3), kbc.F64, 1e-13), ((300, 5, 3), kbc.F32_DEV, 1e-6),
+               ((300, 5, 3), kbc.F32_DEV_X, 3e-8), ((300, 5, 3), kbc.F16_DEV, 1e-4),
+               ((520, 400, 3), kbc.F64, 1e-13), ((520, 400, 3), kbc.F32_DEV_X, 1e-7)]
+
+
+@pytest.mark.parametrize("shape,dtype,tol", ORDER_CASES)
+def test_workgroup_orders_with_ragged_grids(orc, shape, dtype, tol):
+    """In-place (AA) populations after 7 steps, both sweeps, against the
+    oracle, in the workgroup orders the box takes."""
+    u = inputs.hit(shape, 2.0, 0.04, seed=13)
+    nu = 1e-3
+    if shape not in _ORDER_ORACLE:
+        _ORDER_ORACLE[shape] = _oracle_run(orc, u, nu, 7)
+    F = _ORDER_ORACLE[shape]
+    with _box(shape, nu, dtype, streaming=kbc.AA) as b:
+        b.init_velocity(u)
+        b.step(7)
+        err = np.abs(b.populations() - F).max()
+    say(f"workgroup order {shape} dtype={dtype}: max|df|={err:.3e} (bound {tol:.0e})")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("gamma_kind", ["lbgk", "rlb", "rlb_central"])
 def test_forced_gamma_paths(orc, gamma_kind):
     shape = (12, 10, 8)
